@@ -1,0 +1,171 @@
+/*
+ * eslb — fourth-order entropy-stable lattice Boltzmann time loop on gfx950 (MI355X).
+ *
+ * C ABI of libeslb.so.  Method: Bellotti, Helluy, Navoret, "Fourth-order
+ * entropy-stable lattice Boltzmann schemes for hyperbolic systems"
+ * (arXiv 2403.13406).  Every entry point cites the passage that defines what it
+ * computes.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ *  - Precision: every value is IEEE binary64.
+ *  - Pointers named *_dev are device pointers (HIP global memory) owned by the
+ *    caller; the library never frees them and never keeps them after the call
+ *    returns.  The library owns only its context, a small device block of status
+ *    counters and reduction scratch, and (batch) a descriptor table.
+ *  - Distribution layout ("state"): q*M planes of nx*ny doubles, plane
+ *    p = k*M + m (k the discrete velocity, m the conserved component), x fastest
+ *    inside a plane.  Velocity order: D1Q2 (+, -) (Sec. 1.2.1); D2Q4
+ *    (+x, +y, -x, -y) (Sec. 1.2.2).  Conserved-moment arrays u hold M planes of
+ *    nx*ny doubles in the same order as the system's variables.
+ *  - Transport (eq. transportPhase) moves no data: the context keeps one integer
+ *    offset o_k per velocity (cells travelled along V_k/V), and logical
+ *    f_k(x) lives at storage position x - o_k (V_k/V), periodic.  f_dev alone is
+ *    therefore not the logical state; read it with eslb_moments / eslb_gather,
+ *    or save the offsets with eslb_get_offsets.
+ *  - Streams: device work is enqueued asynchronously on the stream given to
+ *    eslb_create (NULL = the null stream) unless a call says it synchronises.
+ *  - Return codes: 0 = ESLB_OK, negative = error (nothing or only part of the
+ *    work was done; eslb_last_error has the message), positive = warning (the
+ *    work was done).  Device-side conditions (inadmissible state, NaN, omega
+ *    fallbacks) are sticky in a device status word and are reported by the next
+ *    synchronising call (eslb_sync_status, eslb_diagnostics, eslb_init_equilibrium).
+ *  - Threading: a context must not be used from two threads at once.
+ */
+#ifndef ESLB_H
+#define ESLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Lattices DdQq^M (Sec. 1.2.1 and 1.2.2). */
+#define ESLB_D1Q2 1
+#define ESLB_D2Q4 2
+
+/* Target systems (Sec. 1.1): examples of Sec. 1.2, 2D Burgers of Sec. 3.3,
+ * Euler of Sec. 6.3.  M = 1 (advection, Burgers), d+1 (shallow water),
+ * d+2 (Euler, D2Q4 only). */
+#define ESLB_ADVECTION 0     /* phi^j = a_j u,        param = {a_x, a_y}          */
+#define ESLB_BURGERS 1       /* phi^j = b_j u^2 / 2,  param = {b_x, b_y}          */
+#define ESLB_SHALLOW_WATER 2 /* (h, hu[, hv]),        param = {g}                 */
+#define ESLB_EULER 3         /* (rho, rho u, rho v, E), param = {gamma}           */
+
+/* Relaxation parameter (eq. relaxationDiscretizationOmega, eq. variableOmegaProblem). */
+#define ESLB_OMEGA_FIXED 0    /* omega = problem.omega at every node (2 in Sec. 2-3) */
+#define ESLB_OMEGA_ENTROPIC 1 /* per-node omega with Sigma(R_omega f) = Sigma(f)    */
+
+/* Status codes. */
+#define ESLB_OK 0
+#define ESLB_ERR_INVALID_ARG (-1)
+#define ESLB_ERR_UNSUPPORTED (-2)
+#define ESLB_ERR_HIP (-3)
+#define ESLB_ERR_NOMEM (-4)
+#define ESLB_ERR_INADMISSIBLE (-6) /* h <= 0, rho <= 0 or p <= 0 in some u            */
+#define ESLB_ERR_NAN (-7)          /* a non-finite value appeared in the state        */
+#define ESLB_WARN_OMEGA_FALLBACK 1 /* some node had no entropic root: omega = 1 used  */
+#define ESLB_WARN_T_NOT_MULTIPLE 2 /* T is not a multiple of Delta t (floor applied)  */
+#define ESLB_WARN_SUBCHARACTERISTIC 3 /* V violates the convexity condition somewhere */
+
+/* Problem statement (Sec. 1.1-1.2, Sec. 2.3): lattice, system with its flux
+ * parameters, grid, kinetic velocity V, space step dx, kappa (cells moved by the
+ * shortest transport T(Delta t / 24); 1 in the paper), relaxation choice and
+ * composition variant. */
+typedef struct eslb_problem {
+  int32_t lattice;   /* ESLB_D1Q2 or ESLB_D2Q4                                   */
+  int32_t system;    /* ESLB_ADVECTION .. ESLB_EULER                             */
+  int32_t nx, ny;    /* grid; ny must be 1 for D1Q2; periodic in every direction */
+  int32_t kappa;     /* >= 1                                                     */
+  int32_t relax;     /* ESLB_OMEGA_FIXED or ESLB_OMEGA_ENTROPIC                  */
+  int32_t scheme;    /* 1: Phi of eq. splittingToUse (Scheme I); 2, 3: Schemes II
+                        and III of Sec. 6.1 (projections R_1 added)              */
+  int32_t reserved;  /* must be 0                                                */
+  double V;          /* kinetic velocity, > 0                                    */
+  double dx;         /* space step, > 0                                          */
+  double omega;      /* used when relax == ESLB_OMEGA_FIXED, in (0, 2]           */
+  double param[4];   /* system parameters, see the system constants above       */
+} eslb_problem;
+
+/* Synchronous diagnostics of one state (Sec. 4). */
+typedef struct eslb_diag {
+  double mass[4];        /* sum_x u_m, m < M                                       */
+  double micro_entropy;  /* sum_x Sigma(f) = sum_x sum_k s_k(f_k)                  */
+  double macro_entropy;  /* sum_x S(u)                                             */
+  double omega_min;      /* over entropic relaxations since the last counter reset */
+  double omega_max;      /*   (only tracked after eslb_set_stats(ctx, 1))          */
+  int64_t n_fallback;    /* node relaxations that fell back to omega = 1 since reset */
+  int64_t n_outside;     /* nodes whose populations are outside the convexity domain */
+  int64_t n_inadmissible;/* nodes with inadmissible u (now)                        */
+  int64_t n_nan;         /* nodes with a non-finite population (now)               */
+} eslb_diag;
+
+typedef struct eslb_ctx eslb_ctx;
+
+/* Create a context for one problem (validates it; allocates only the small
+ * status/reduction block).  stream: a hipStream_t, or NULL.  On success *out is
+ * set; destroy it with eslb_destroy. */
+int eslb_create(const eslb_problem* problem, void* stream, eslb_ctx** out);
+void eslb_destroy(eslb_ctx* ctx);
+
+/* q * M * nx * ny * 8: bytes of one state. */
+int eslb_state_bytes(const eslb_ctx* ctx, size_t* bytes);
+/* Number of conserved components M and of velocities q. */
+int eslb_dims(const eslb_ctx* ctx, int32_t* M, int32_t* q);
+
+/* Delta t = 24 kappa dx / V (Sec. 2.3). */
+int eslb_dt(const eslb_ctx* ctx, double* dt);
+/* n = floor(T / Delta t) in binary64 (the paper leaves this open); returns
+ * ESLB_WARN_T_NOT_MULTIPLE when n * Delta t != T. */
+int eslb_steps_for_time(const eslb_ctx* ctx, double T, int64_t* n);
+
+/* f_k = f_k^eq(u) at every node (initial data at equilibrium, Sec. 3.1) and
+ * offsets reset to 0.  u_dev: M planes (read); f_dev: q*M planes (written).
+ * Synchronises; returns ESLB_ERR_INADMISSIBLE if some u is inadmissible and
+ * ESLB_WARN_SUBCHARACTERISTIC if V violates the convexity condition somewhere. */
+int eslb_init_equilibrium(eslb_ctx* ctx, const double* u_dev, double* f_dev);
+
+/* Advance nsteps >= 0 composed steps Phi(Delta t) in place (eq. splittingToUse,
+ * eq. basicBrickSplitting; Schemes II/III of Sec. 6.1 when selected): per step
+ * 18 passes "shift, relax" with shifts kappa * (1, 2 x7, -1, -4, -1, 2 x7) and a
+ * trailing shift of kappa.  Asynchronous. */
+int eslb_step(eslb_ctx* ctx, double* f_dev, int64_t nsteps);
+
+/* One transport T(cells) (eq. transportPhase): offsets only, no device work. */
+int eslb_transport(eslb_ctx* ctx, int32_t cells);
+/* One relaxation pass R_omega at every node with the context's omega choice
+ * (eq. relaxationDiscretizationOmega / eq. variableOmegaProblem).  Asynchronous. */
+int eslb_relax(eslb_ctx* ctx, double* f_dev);
+/* One projection R_1 on the equilibrium (Sec. 6.1).  Asynchronous. */
+int eslb_project(eslb_ctx* ctx, double* f_dev);
+
+/* u = sum_k f_k at every logical node (Sec. 1.2), offsets applied.
+ * f_dev: q*M planes (read); u_dev: M planes (written).  Asynchronous. */
+int eslb_moments(eslb_ctx* ctx, const double* f_dev, double* u_dev);
+/* The logical distributions (offsets applied) copied to out_dev (q*M planes, must
+ * not alias f_dev): out_dev is the state with all offsets 0.  Asynchronous. */
+int eslb_gather(eslb_ctx* ctx, const double* f_dev, double* out_dev);
+
+/* Offsets o_k (q entries, cells travelled along V_k / V). */
+int eslb_get_offsets(const eslb_ctx* ctx, int64_t* offsets);
+int eslb_set_offsets(eslb_ctx* ctx, const int64_t* offsets);
+
+/* Synchronous diagnostics (see eslb_diag).  Returns the sticky status. */
+int eslb_diagnostics(eslb_ctx* ctx, const double* f_dev, eslb_diag* out);
+/* Track omega min/max in every entropic pass (costs a few atomics per block). */
+int eslb_set_stats(eslb_ctx* ctx, int32_t on);
+/* Zero the device counters and the sticky status.  Asynchronous. */
+int eslb_reset_counters(eslb_ctx* ctx);
+/* Synchronise the stream and return the sticky status. */
+int eslb_sync_status(eslb_ctx* ctx);
+
+const char* eslb_status_string(int code);
+const char* eslb_last_error(const eslb_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESLB_H */

@@ -1,0 +1,690 @@
+// libeslb: C ABI and HIP kernels of the fourth-order entropy-stable lattice
+// Boltzmann time loop (Bellotti, Helluy, Navoret, arXiv 2403.13406) for gfx950.
+//
+// Design (MI355X):
+//  * SoA state, q*M planes of nx*ny binary64, x fastest.
+//  * Transport (eq. transportPhase) is integer shifts of whole planes; it is
+//    kept as per-velocity offsets and folded into the addressing of the next
+//    relaxation pass, so a stage "shift then relax" is exactly one read and one
+//    write of every population, in place.  Along x the shifted read of a row is
+//    contiguous except at the periodic wrap; along y it is a whole other row:
+//    every access of a wavefront is coalesced.
+//  * One thread relaxes one node in registers; the entropy-limited omega
+//    (eq. variableOmegaProblem) is solved there, no memory traffic.
+//  * Composed step (eq. splittingToUse with eq. basicBrickSplitting): 18 passes
+//    "shift, relax" with shifts kappa*(1, 2x7, -1, -4, -1, 2x7) + trailing kappa.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "eslb.h"
+#include "eslb_internal.hpp"
+#include "eslb_systems.hpp"
+
+using namespace eslb;
+
+namespace {
+
+// ------------------------------------------------------------------ kernels
+
+template <int D>
+__device__ __forceinline__ long long storage_index(const Grid& g, int k, int x, int y) {
+  if (Lat<D>::axis(k) == 0) {
+    int xs = x + g.sh[k];
+    if (xs >= g.nx) xs -= g.nx;
+    return (long long)y * g.nx + xs;
+  }
+  int ys = y + g.sh[k];
+  if (ys >= g.ny) ys -= g.ny;
+  return (long long)ys * g.nx + x;
+}
+
+__device__ __forceinline__ void record_flags(DevStats* st, unsigned flags) {
+  if (flags) {
+    atomicOr(&st->flags, flags);
+    if (flags & FLAG_FALLBACK) atomicAdd(&st->n_fallback, 1ull);
+  }
+}
+
+__device__ __forceinline__ void record_omega(DevStats* st, bool act, double om) {
+  double mn = act ? om : INFINITY, mx = act ? om : -INFINITY;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mn = fmin(mn, __shfl_xor(mn, o));
+    mx = fmax(mx, __shfl_xor(mx, o));
+  }
+  if (__lane_id() == 0 && mn <= mx) {
+    atomicMin(&st->om_min_bits, (unsigned long long)__double_as_longlong(mn));
+    atomicMax(&st->om_max_bits, (unsigned long long)__double_as_longlong(mx));
+  }
+}
+
+// One relaxation pass (the shift that precedes it is in g.sh).
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_stage(Grid g, Phys P, int mode, int track, DevStats* st) {
+  constexpr int Q = S::Q, M = S::M;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const bool act = (x < g.nx) && (y < g.ny);
+  unsigned flags = 0;
+  double om = 2.0;
+  if (act) {
+    long long id[Q];
+    double f[Q][M];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      id[k] = storage_index<D>(g, k, x, y);
+#pragma unroll
+      for (int m = 0; m < M; ++m) f[k][m] = g.f[(long long)(k * M + m) * g.plane + id[k]];
+    }
+    om = relax_node<S>(f, mode, P, flags);
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        fin &= isfinite(f[k][m]);
+        g.f[(long long)(k * M + m) * g.plane + id[k]] = f[k][m];
+      }
+    if (!fin) flags |= FLAG_NAN;
+  }
+  record_flags(st, flags);
+  if (track) record_omega(st, act, om);
+}
+
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_init(const double* __restrict__ u, double* __restrict__ f, long long plane,
+                                               int nx, int ny, Phys P, DevStats* st) {
+  constexpr int Q = S::Q, M = S::M;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= nx || y >= ny) return;
+  const long long i = (long long)y * nx + x;
+  double uu[M], feq[Q][M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) uu[m] = u[(long long)m * plane + i];
+  Eq<S>::equilibrium(uu, feq, P);
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[(long long)(k * M + m) * plane + i] = feq[k][m];
+  typename S::Node c;
+  unsigned flags = 0;
+  if (!S::prepare(uu, c, P)) flags |= FLAG_INADMISSIBLE;
+  else if (!S::subchar(c, P)) flags |= FLAG_SUBCHAR;
+  if (flags) atomicOr(&st->flags, flags);
+}
+
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_moments(Grid g, double* __restrict__ u) {
+  constexpr int Q = S::Q, M = S::M;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= g.nx || y >= g.ny) return;
+  long long id[Q];
+#pragma unroll
+  for (int k = 0; k < Q; ++k) id[k] = storage_index<D>(g, k, x, y);
+  const long long i = (long long)y * g.nx + x;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double acc = g.f[(long long)m * g.plane + id[0]];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) acc += g.f[(long long)(k * M + m) * g.plane + id[k]];
+    u[(long long)m * g.plane + i] = acc;
+  }
+}
+
+template <class S, int D>
+__global__ __launch_bounds__(256) void k_gather(Grid g, double* __restrict__ out) {
+  constexpr int Q = S::Q, M = S::M;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  if (x >= g.nx || y >= g.ny) return;
+  const long long i = (long long)y * g.nx + x;
+#pragma unroll
+  for (int k = 0; k < Q; ++k) {
+    const long long id = storage_index<D>(g, k, x, y);
+#pragma unroll
+    for (int m = 0; m < M; ++m) out[(long long)(k * M + m) * g.plane + i] = g.f[(long long)(k * M + m) * g.plane + id];
+  }
+}
+
+// Diagnostics, pass 1: per-block partial sums in a fixed tree order.
+// Layout of a block's partials: mass[M], micro, macro (NV = M + 2 doubles).
+constexpr int kDiagThreads = 256;
+
+template <class S, int D>
+__global__ __launch_bounds__(kDiagThreads) void k_diag(Grid g, Phys P, double* partials, DevStats* st) {
+  constexpr int Q = S::Q, M = S::M, NV = M + 2;
+  __shared__ double red[NV][kDiagThreads];
+  const int tid = threadIdx.x;
+  const long long ncell = (long long)g.nx * g.ny;
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  unsigned long long n_out = 0, n_inad = 0, n_nan = 0;
+  for (long long cidx = (long long)blockIdx.x * kDiagThreads + tid; cidx < ncell;
+       cidx += (long long)gridDim.x * kDiagThreads) {
+    const int x = (int)(cidx % g.nx), y = (int)(cidx / g.nx);
+    double f[Q][M], u[M];
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const long long id = storage_index<D>(g, k, x, y);
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        f[k][m] = g.f[(long long)(k * M + m) * g.plane + id];
+        fin &= isfinite(f[k][m]);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      double a = f[0][m];
+#pragma unroll
+      for (int k = 1; k < Q; ++k) a += f[k][m];
+      u[m] = a;
+      acc[m] += a;
+    }
+    if (!fin) { ++n_nan; continue; }
+    typename S::Node c;
+    if (!S::prepare(u, c, P)) { ++n_inad; continue; }
+    double feq[Q][M], d[Q][M];
+    Eq<S>::equilibrium(u, feq, P);
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m) d[k][m] = f[k][m] - feq[k][m];
+    double F = 0.0, dF = 0.0;
+    const bool ok = fsum<S>(c, feq, d, 1.0, F, dF, P);
+    const double Su = S::macro_entropy(c, P);
+    acc[M + 1] += Su;
+    if (ok) acc[M] += Su + F; else ++n_out;
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) red[v][tid] = acc[v];
+  __syncthreads();
+  for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) red[v][tid] += red[v][tid + s];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) partials[(long long)blockIdx.x * NV + v] = red[v][0];
+  }
+  if (n_out) atomicAdd(&st->n_outside, n_out);
+  if (n_inad) atomicAdd(&st->n_inadmissible, n_inad);
+  if (n_nan) atomicAdd(&st->n_nan, n_nan);
+}
+
+// Diagnostics, pass 2: one block sums the partials in a fixed order.
+__global__ __launch_bounds__(kDiagThreads) void k_diag_final(const double* partials, int nblocks, int nv, double* out) {
+  __shared__ double red[kDiagThreads];
+  for (int v = 0; v < nv; ++v) {
+    double a = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kDiagThreads) a += partials[(long long)b * nv + v];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int s = kDiagThreads / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset(DevStats* st) {
+  st->n_fallback = 0;
+  st->om_min_bits = 0x7ff0000000000000ull;  // +inf
+  st->om_max_bits = 0;                      // +0
+  st->flags = 0;
+  st->n_outside = 0;
+  st->n_inadmissible = 0;
+  st->n_nan = 0;
+}
+
+__global__ void k_reset_now(DevStats* st) {
+  st->n_outside = 0;
+  st->n_inadmissible = 0;
+  st->n_nan = 0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host side
+
+namespace eslb {
+
+thread_local std::string g_last_error;
+void eslb_set_global_error(const std::string& msg) { g_last_error = msg; }
+
+static int set_err(eslb_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+static int hip_check(eslb_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return ESLB_OK;
+  return set_err(c, ESLB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+static long long pmod(long long a, long long n) {
+  long long r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+Grid make_grid(const eslb_ctx* c, double* f) {
+  Grid g;
+  g.f = f;
+  g.nx = c->pb.nx;
+  g.ny = c->pb.ny;
+  g.plane = (long long)c->pb.nx * c->pb.ny;
+  for (int k = 0; k < 4; ++k) g.sh[k] = 0;
+  for (int k = 0; k < c->q; ++k) {
+    const int axis = (c->d == 1) ? 0 : (k & 1);
+    const int sign = (k < c->q / 2) ? 1 : -1;
+    const long long n = axis == 0 ? c->pb.nx : c->pb.ny;
+    // logical f_k(x) is stored at x - o_k sign_k along the axis: storage shift -sign*o_k
+    g.sh[k] = (int)pmod(-(long long)sign * c->off[k], n);
+  }
+  return g;
+}
+
+void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
+  if (c->d == 1) {
+    block = dim3(256, 1, 1);
+    grid = dim3((c->pb.nx + 255) / 256, 1, 1);
+  } else {
+    const int bx = c->pb.nx >= 64 ? 64 : 32;
+    const int by = 256 / bx;
+    block = dim3(bx, by, 1);
+    grid = dim3((c->pb.nx + bx - 1) / bx, (c->pb.ny + by - 1) / by, 1);
+  }
+}
+
+#define ESLB_DISPATCH(KIND, CALL)                          \
+  switch (KIND) {                                          \
+    case KIND_ADV1: CALL(Advection<1>, 1); break;          \
+    case KIND_ADV2: CALL(Advection<2>, 2); break;          \
+    case KIND_BUR1: CALL(Burgers<1>, 1); break;            \
+    case KIND_BUR2: CALL(Burgers<2>, 2); break;            \
+    case KIND_SW1: CALL(ShallowWater<1>, 1); break;        \
+    case KIND_SW2: CALL(ShallowWater<2>, 2); break;        \
+    case KIND_EU2: CALL(Euler2, 2); break;                 \
+    default: break;                                        \
+  }
+
+int launch_stage(eslb_ctx* c, double* f, int mode) {
+  const Grid g = make_grid(c, f);
+  dim3 grid, block;
+  launch_shape(c, grid, block);
+  const int track = (mode == 1) ? c->track : 0;
+  Phys P = c->phys;
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D>), grid, block, 0, c->stream, g, P, mode, track, c->st)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  return hip_check(c, hipGetLastError(), "stage kernel launch");
+}
+
+static int kind_of(const eslb_problem& p, int* d, int* q, int* M) {
+  if (p.lattice == ESLB_D1Q2) {
+    *d = 1; *q = 2;
+    switch (p.system) {
+      case ESLB_ADVECTION: *M = 1; return KIND_ADV1;
+      case ESLB_BURGERS: *M = 1; return KIND_BUR1;
+      case ESLB_SHALLOW_WATER: *M = 2; return KIND_SW1;
+      default: return -1;
+    }
+  }
+  if (p.lattice == ESLB_D2Q4) {
+    *d = 2; *q = 4;
+    switch (p.system) {
+      case ESLB_ADVECTION: *M = 1; return KIND_ADV2;
+      case ESLB_BURGERS: *M = 1; return KIND_BUR2;
+      case ESLB_SHALLOW_WATER: *M = 3; return KIND_SW2;
+      case ESLB_EULER: *M = 4; return KIND_EU2;
+      default: return -1;
+    }
+  }
+  return -1;
+}
+
+int validate_problem(const eslb_problem* p, std::string& why, int* kind, int* d, int* q, int* M) {
+  if (!p) { why = "problem is NULL"; return ESLB_ERR_INVALID_ARG; }
+  if (p->lattice != ESLB_D1Q2 && p->lattice != ESLB_D2Q4) { why = "unknown lattice"; return ESLB_ERR_INVALID_ARG; }
+  if (p->system < ESLB_ADVECTION || p->system > ESLB_EULER) { why = "unknown system"; return ESLB_ERR_INVALID_ARG; }
+  const int k = kind_of(*p, d, q, M);
+  if (k < 0) { why = "lattice/system combination not supported (Euler needs D2Q4)"; return ESLB_ERR_UNSUPPORTED; }
+  *kind = k;
+  if (p->nx < 1 || p->ny < 1) { why = "nx and ny must be >= 1"; return ESLB_ERR_INVALID_ARG; }
+  if (p->lattice == ESLB_D1Q2 && p->ny != 1) { why = "D1Q2 needs ny == 1"; return ESLB_ERR_INVALID_ARG; }
+  if ((long long)p->nx * p->ny > (1ll << 40)) { why = "grid too large"; return ESLB_ERR_INVALID_ARG; }
+  if (p->kappa < 1) { why = "kappa must be >= 1"; return ESLB_ERR_INVALID_ARG; }
+  if (!(p->V > 0.0) || !std::isfinite(p->V)) { why = "V must be > 0"; return ESLB_ERR_INVALID_ARG; }
+  if (!(p->dx > 0.0) || !std::isfinite(p->dx)) { why = "dx must be > 0"; return ESLB_ERR_INVALID_ARG; }
+  if (p->relax != ESLB_OMEGA_FIXED && p->relax != ESLB_OMEGA_ENTROPIC) { why = "unknown relax mode"; return ESLB_ERR_INVALID_ARG; }
+  if (p->relax == ESLB_OMEGA_FIXED && !(p->omega > 0.0 && p->omega <= 2.0)) {
+    why = "fixed omega must lie in (0, 2]";
+    return ESLB_ERR_INVALID_ARG;
+  }
+  if (p->scheme < 1 || p->scheme > 3) { why = "scheme must be 1, 2 or 3"; return ESLB_ERR_INVALID_ARG; }
+  if (p->reserved != 0) { why = "reserved must be 0"; return ESLB_ERR_INVALID_ARG; }
+  if (p->system == ESLB_SHALLOW_WATER && !(p->param[0] > 0.0)) { why = "shallow water needs g > 0"; return ESLB_ERR_INVALID_ARG; }
+  if (p->system == ESLB_EULER && !(p->param[0] > 1.0)) { why = "Euler needs gamma > 1"; return ESLB_ERR_INVALID_ARG; }
+  return ESLB_OK;
+}
+
+Phys make_phys(const eslb_problem& p, int q) {
+  Phys P;
+  P.V = p.V;
+  P.inv2V = 1.0 / (2.0 * p.V);
+  P.w = 1.0 / q;
+  P.W0 = 2.0 * P.w * p.V;
+  P.p0 = p.param[0];
+  P.p1 = p.param[1];
+  P.omega = p.omega;
+  return P;
+}
+
+void build_schedule(eslb_ctx* c) {
+  // eq. splittingToUse with eq. basicBrickSplitting, consecutive shifts merged
+  // (transport moves no data, so merging is only bookkeeping).
+  const int k = c->pb.kappa;
+  c->passes.clear();
+  if (c->pb.scheme == 3) {
+    // Scheme III: R_1 after every brick (Sec. 6.1)
+    for (int b = 0; b < 9; ++b) {
+      const int s = (b == 4) ? -2 * k : k;  // brick psi(dt/6) moves (1,2,1)k, psi(-dt/3) (-2,-4,-2)k
+      c->passes.push_back({s, PASS_RELAX});
+      c->passes.push_back({2 * s, PASS_RELAX});
+      c->passes.push_back({s, PASS_PROJECT});
+    }
+    c->trailing = 0;
+    return;
+  }
+  const int shifts[18] = {1, 2, 2, 2, 2, 2, 2, 2, -1, -4, -1, 2, 2, 2, 2, 2, 2, 2};
+  for (int i = 0; i < 18; ++i) c->passes.push_back({shifts[i] * k, PASS_RELAX});
+  if (c->pb.scheme == 2) {
+    c->passes.push_back({k, PASS_PROJECT});  // Scheme II: R_1 after Phi
+    c->trailing = 0;
+  } else {
+    c->trailing = k;
+  }
+}
+
+void add_offsets(eslb_ctx* c, long long s) {
+  for (int k = 0; k < c->q; ++k) c->off[k] += s;
+}
+
+int run_pass(eslb_ctx* c, double* f, int shift, int op) {
+  add_offsets(c, shift);
+  const int mode = (op == PASS_PROJECT) ? 0 : c->pb.relax;
+  if (op == PASS_PROJECT) {
+    const double keep = c->phys.omega;
+    c->phys.omega = 1.0;
+    const int rc = launch_stage(c, f, 0);
+    c->phys.omega = keep;
+    return rc;
+  }
+  return launch_stage(c, f, mode);
+}
+
+}  // namespace eslb
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* eslb_status_string(int code) {
+  switch (code) {
+    case ESLB_OK: return "ok";
+    case ESLB_ERR_INVALID_ARG: return "invalid argument";
+    case ESLB_ERR_UNSUPPORTED: return "unsupported lattice/system";
+    case ESLB_ERR_HIP: return "HIP runtime error";
+    case ESLB_ERR_NOMEM: return "out of memory";
+    case ESLB_ERR_INADMISSIBLE: return "inadmissible state (h, rho or p <= 0)";
+    case ESLB_ERR_NAN: return "non-finite value in the state";
+    case ESLB_WARN_OMEGA_FALLBACK: return "warning: entropic omega fell back to 1 at some nodes";
+    case ESLB_WARN_T_NOT_MULTIPLE: return "warning: T is not a multiple of dt";
+    case ESLB_WARN_SUBCHARACTERISTIC: return "warning: sub-characteristic condition violated";
+    default: return "unknown status";
+  }
+}
+
+const char* eslb_last_error(const eslb_ctx* c) { return c ? c->err.c_str() : eslb::g_last_error.c_str(); }
+
+int eslb_create(const eslb_problem* p, void* stream, eslb_ctx** out) {
+  if (!out) return ESLB_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::string why;
+  int kind = 0, d = 0, q = 0, M = 0;
+  const int rc = validate_problem(p, why, &kind, &d, &q, &M);
+  if (rc != ESLB_OK) {
+    eslb_set_global_error(why);
+    return rc;
+  }
+  eslb_ctx* c = new eslb_ctx();
+  c->pb = *p;
+  c->kind = kind;
+  c->d = d;
+  c->q = q;
+  c->M = M;
+  c->stream = (hipStream_t)stream;
+  for (int k = 0; k < 4; ++k) c->off[k] = 0;
+  c->phys = make_phys(*p, q);
+  build_schedule(c);
+  c->diag_blocks = 1024;
+  const int nv = M + 2;
+  hipError_t e = hipMalloc(&c->st, sizeof(DevStats));
+  if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * ((size_t)c->diag_blocks * nv + nv));
+  if (e != hipSuccess) {
+    eslb_set_global_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+    if (c->st) (void)hipFree(c->st);
+    delete c;
+    return ESLB_ERR_NOMEM;
+  }
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, c->stream, c->st);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    eslb_set_global_error(std::string("reset kernel: ") + hipGetErrorString(e));
+    (void)hipFree(c->st);
+    (void)hipFree(c->partials);
+    delete c;
+    return ESLB_ERR_HIP;
+  }
+  *out = c;
+  return ESLB_OK;
+}
+
+void eslb_destroy(eslb_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  if (c->st) (void)hipFree(c->st);
+  if (c->partials) (void)hipFree(c->partials);
+  delete c;
+}
+
+int eslb_state_bytes(const eslb_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return ESLB_ERR_INVALID_ARG;
+  *bytes = (size_t)c->q * c->M * (size_t)c->pb.nx * c->pb.ny * sizeof(double);
+  return ESLB_OK;
+}
+
+int eslb_dims(const eslb_ctx* c, int32_t* M, int32_t* q) {
+  if (!c) return ESLB_ERR_INVALID_ARG;
+  if (M) *M = c->M;
+  if (q) *q = c->q;
+  return ESLB_OK;
+}
+
+int eslb_dt(const eslb_ctx* c, double* dt) {
+  if (!c || !dt) return ESLB_ERR_INVALID_ARG;
+  *dt = 24.0 * c->pb.kappa * c->pb.dx / c->pb.V;
+  return ESLB_OK;
+}
+
+int eslb_steps_for_time(const eslb_ctx* c, double T, int64_t* n) {
+  if (!c || !n || !(T >= 0.0) || !std::isfinite(T)) return ESLB_ERR_INVALID_ARG;
+  const double dt = 24.0 * c->pb.kappa * c->pb.dx / c->pb.V;
+  const double r = std::floor(T / dt);
+  *n = (int64_t)r;
+  return (r * dt == T) ? ESLB_OK : ESLB_WARN_T_NOT_MULTIPLE;
+}
+
+int eslb_init_equilibrium(eslb_ctx* c, const double* u, double* f) {
+  if (!c || !u || !f) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  for (int k = 0; k < 4; ++k) c->off[k] = 0;
+  dim3 grid, block;
+  launch_shape(c, grid, block);
+  const long long plane = (long long)c->pb.nx * c->pb.ny;
+  const int nx = c->pb.nx, ny = c->pb.ny;
+  Phys P = c->phys;
+#define CALL(S, D) hipLaunchKernelGGL((k_init<S, D>), grid, block, 0, c->stream, u, f, plane, nx, ny, P, c->st)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  int rc = hip_check(c, hipGetLastError(), "init kernel launch");
+  if (rc != ESLB_OK) return rc;
+  return eslb_sync_status(c);
+}
+
+int eslb_step(eslb_ctx* c, double* f, int64_t nsteps) {
+  if (!c || !f || nsteps < 0) return set_err(c, ESLB_ERR_INVALID_ARG, "bad argument to eslb_step");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    for (const Pass& ps : c->passes) {
+      const int rc = run_pass(c, f, ps.shift, ps.op);
+      if (rc != ESLB_OK) return rc;
+    }
+    add_offsets(c, c->trailing);
+  }
+  return ESLB_OK;
+}
+
+int eslb_transport(eslb_ctx* c, int32_t cells) {
+  if (!c) return ESLB_ERR_INVALID_ARG;
+  add_offsets(c, cells);
+  return ESLB_OK;
+}
+
+int eslb_relax(eslb_ctx* c, double* f) {
+  if (!c || !f) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  return launch_stage(c, f, c->pb.relax);
+}
+
+int eslb_project(eslb_ctx* c, double* f) {
+  if (!c || !f) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  return run_pass(c, f, 0, PASS_PROJECT);
+}
+
+int eslb_moments(eslb_ctx* c, const double* f, double* u) {
+  if (!c || !f || !u) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  const Grid g = make_grid(c, const_cast<double*>(f));
+  dim3 grid, block;
+  launch_shape(c, grid, block);
+#define CALL(S, D) hipLaunchKernelGGL((k_moments<S, D>), grid, block, 0, c->stream, g, u)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  return hip_check(c, hipGetLastError(), "moments kernel launch");
+}
+
+int eslb_gather(eslb_ctx* c, const double* f, double* out) {
+  if (!c || !f || !out) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  if (f == out) return set_err(c, ESLB_ERR_INVALID_ARG, "eslb_gather: out must not alias f");
+  const Grid g = make_grid(c, const_cast<double*>(f));
+  dim3 grid, block;
+  launch_shape(c, grid, block);
+#define CALL(S, D) hipLaunchKernelGGL((k_gather<S, D>), grid, block, 0, c->stream, g, out)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  return hip_check(c, hipGetLastError(), "gather kernel launch");
+}
+
+int eslb_get_offsets(const eslb_ctx* c, int64_t* o) {
+  if (!c || !o) return ESLB_ERR_INVALID_ARG;
+  for (int k = 0; k < c->q; ++k) o[k] = c->off[k];
+  return ESLB_OK;
+}
+
+int eslb_set_offsets(eslb_ctx* c, const int64_t* o) {
+  if (!c || !o) return ESLB_ERR_INVALID_ARG;
+  for (int k = 0; k < c->q; ++k) c->off[k] = o[k];
+  return ESLB_OK;
+}
+
+int eslb_set_stats(eslb_ctx* c, int32_t on) {
+  if (!c) return ESLB_ERR_INVALID_ARG;
+  c->track = on ? 1 : 0;
+  return ESLB_OK;
+}
+
+int eslb_reset_counters(eslb_ctx* c) {
+  if (!c) return ESLB_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(1), 0, c->stream, c->st);
+  return hip_check(c, hipGetLastError(), "reset kernel launch");
+}
+
+int eslb_sync_status(eslb_ctx* c) {
+  if (!c) return ESLB_ERR_INVALID_ARG;
+  int rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+  if (rc != ESLB_OK) return rc;
+  DevStats h;
+  rc = hip_check(c, hipMemcpy(&h, c->st, sizeof(h), hipMemcpyDeviceToHost), "status readback");
+  if (rc != ESLB_OK) return rc;
+  if (h.flags & FLAG_NAN) return set_err(c, ESLB_ERR_NAN, "non-finite value in the state");
+  if (h.flags & FLAG_INADMISSIBLE) return set_err(c, ESLB_ERR_INADMISSIBLE, "inadmissible conserved state");
+  if (h.flags & FLAG_FALLBACK) return ESLB_WARN_OMEGA_FALLBACK;
+  if (h.flags & FLAG_SUBCHAR) return ESLB_WARN_SUBCHARACTERISTIC;
+  return ESLB_OK;
+}
+
+int eslb_diagnostics(eslb_ctx* c, const double* f, eslb_diag* out) {
+  if (!c || !f || !out) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  const Grid g = make_grid(c, const_cast<double*>(f));
+  const long long ncell = (long long)c->pb.nx * c->pb.ny;
+  long long nb = (ncell + kDiagThreads - 1) / kDiagThreads;
+  if (nb > c->diag_blocks) nb = c->diag_blocks;
+  const int nblocks = (int)nb;
+  const int nv = c->M + 2;
+  // counters of the "now" quantities start from zero (a kernel, not a memset node)
+  hipLaunchKernelGGL(k_reset_now, dim3(1), dim3(1), 0, c->stream, c->st);
+  int rc = hip_check(c, hipGetLastError(), "reset kernel launch");
+  if (rc != ESLB_OK) return rc;
+  Phys P = c->phys;
+#define CALL(S, D) hipLaunchKernelGGL((k_diag<S, D>), dim3(nblocks), dim3(kDiagThreads), 0, c->stream, g, P, c->partials, c->st)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  rc = hip_check(c, hipGetLastError(), "diagnostics kernel launch");
+  if (rc != ESLB_OK) return rc;
+  double* fin = c->partials + (size_t)c->diag_blocks * nv;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, c->stream, c->partials, nblocks, nv, fin);
+  rc = hip_check(c, hipGetLastError(), "diagnostics final launch");
+  if (rc != ESLB_OK) return rc;
+  double sums[6];
+  DevStats h;
+  rc = hip_check(c, hipMemcpyAsync(sums, fin, sizeof(double) * nv, hipMemcpyDeviceToHost, c->stream), "readback");
+  if (rc == ESLB_OK) rc = hip_check(c, hipMemcpyAsync(&h, c->st, sizeof(h), hipMemcpyDeviceToHost, c->stream), "readback");
+  if (rc == ESLB_OK) rc = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+  if (rc != ESLB_OK) return rc;
+  std::memset(out, 0, sizeof(*out));
+  for (int m = 0; m < c->M; ++m) out->mass[m] = sums[m];
+  out->micro_entropy = sums[c->M];
+  out->macro_entropy = sums[c->M + 1];
+  double mn, mx;
+  std::memcpy(&mn, &h.om_min_bits, sizeof(double));
+  std::memcpy(&mx, &h.om_max_bits, sizeof(double));
+  out->omega_min = mn;
+  out->omega_max = mx;
+  out->n_fallback = (int64_t)h.n_fallback;
+  out->n_outside = (int64_t)h.n_outside;
+  out->n_inadmissible = (int64_t)h.n_inadmissible;
+  out->n_nan = (int64_t)h.n_nan;
+  return eslb_sync_status(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,58 @@
+// Host/device data shared by the translation units of libeslb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "eslb.h"
+#include "eslb_systems.hpp"
+
+namespace eslb {
+
+// Device-side status block (one per context).
+struct DevStats {
+  unsigned long long n_fallback;   // node relaxations that used omega = 1 (no entropic root)
+  unsigned long long om_min_bits;  // bit pattern of the smallest omega (omega > 0)
+  unsigned long long om_max_bits;  // bit pattern of the largest omega
+  unsigned int flags;              // FLAG_* (sticky)
+  unsigned int pad;
+  unsigned long long n_outside;    // diagnostics: nodes outside the convexity domain
+  unsigned long long n_inadmissible;
+  unsigned long long n_nan;
+};
+
+// One state as seen by a kernel: planes and per-velocity storage shifts.
+struct Grid {
+  double* f;
+  long long plane;  // nx * ny
+  int nx, ny;
+  int sh[4];        // logical node x of velocity k is stored at x + sh[k] (mod n) along its axis
+};
+
+enum Kind { KIND_ADV1, KIND_ADV2, KIND_BUR1, KIND_BUR2, KIND_SW1, KIND_SW2, KIND_EU2 };
+enum PassOp { PASS_RELAX = 0, PASS_PROJECT = 1 };
+struct Pass {
+  int shift;  // cells moved by the transport that precedes the relaxation
+  int op;     // PASS_RELAX (context's omega) or PASS_PROJECT (R_1)
+};
+
+void eslb_set_global_error(const std::string& msg);
+
+}  // namespace eslb
+
+struct eslb_ctx {
+  eslb_problem pb;
+  int kind = 0, d = 1, q = 2, M = 1;
+  hipStream_t stream = nullptr;
+  long long off[4] = {0, 0, 0, 0};  // logical offsets o_k (cells travelled along V_k / V)
+  eslb::Phys phys;
+  std::vector<eslb::Pass> passes;   // one composed step
+  int trailing = 0;                 // shift after the last pass of a step
+  eslb::DevStats* st = nullptr;
+  double* partials = nullptr;
+  int diag_blocks = 0;
+  int track = 0;
+  std::string err;
+};

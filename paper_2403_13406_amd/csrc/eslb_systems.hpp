@@ -1,0 +1,419 @@
+// Per-node physics of the fourth-order entropy-stable lattice Boltzmann scheme,
+// device side (gfx950, binary64).
+//
+// Sec. 1.2: equilibria f_k^eq = w u + sigma_k phi^{n_k}(u) / (2V), w = 1/q, with
+// n_k the axis and sigma_k the sign of V_k (D1Q2: +, -; D2Q4: +x, +y, -x, -y).
+//
+// Entropy-limited relaxation (Sec. 4, eq. variableOmegaProblem; Sec. 5.1): with
+// d = f - f^eq and lambda = omega - 1, Sigma(f^eq + t d) = S(u) + F(t),
+//   F(t) = sum_k B_k(t),  B_k = Bregman divergence of s_k between f_k^eq + t d_k
+// and f_k^eq.  omega solves F(-lambda) = F(1).  B_k is evaluated from the
+// "population state" offset U_k - u, where f_k^eq(U_k) = f_k^eq(u) + t d_k, and
+// that offset is obtained from an equation written in increments (e = t d) so
+// that nothing O(1) cancels: the distance from equilibrium is factored out.
+//
+// Each system provides
+//   flux(u, j, phi)        phi^j(u)
+//   prepare(u, c)          node constants; false if u is inadmissible
+//   subchar(c)             convexity (sub-characteristic) condition at the node
+//   macro_entropy(c)       S(u)
+//   bregman<k>(c, feq_k, e, B, dv)   B_k and v(U_k) - v(u); false outside the domain
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace eslb {
+
+struct Phys {
+  double V;      // kinetic velocity
+  double inv2V;  // 1 / (2V)
+  double w;      // 1 / q
+  double W0;     // 2 w V
+  double p0, p1; // system parameters (a_x,a_y | b_x,b_y | g | gamma)
+  double omega;  // fixed relaxation parameter
+};
+
+template <int D> struct Lat;
+template <> struct Lat<1> {
+  static constexpr int Q = 2;
+  __host__ __device__ static constexpr int axis(int) { return 0; }
+  __host__ __device__ static constexpr int sign(int k) { return k == 0 ? 1 : -1; }
+};
+template <> struct Lat<2> {
+  static constexpr int Q = 4;
+  __host__ __device__ static constexpr int axis(int k) { return k & 1; }
+  __host__ __device__ static constexpr int sign(int k) { return k < 2 ? 1 : -1; }
+};
+
+// ---------------------------------------------------------------- advection
+// phi^j = a_j u, S = u^2/2; s_k(x) = x^2 / (2 w_k), w_k = w + sigma a_n / (2V)
+// (Example "Linear transport equation", Sec. 1.2.1 and 1.2.2).
+template <int D> struct Advection {
+  static constexpr int M = 1, Q = Lat<D>::Q;
+  struct Node { double u; };
+  __device__ static double a(int j, const Phys& P) { return j == 0 ? P.p0 : P.p1; }
+  __device__ static void flux(const double* u, int j, double* phi, const Phys& P) { phi[0] = a(j, P) * u[0]; }
+  __device__ static bool prepare(const double* u, Node& c, const Phys&) { c.u = u[0]; return true; }
+  __device__ static bool subchar(const Node&, const Phys& P) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ok &= P.w + Lat<D>::sign(k) * a(Lat<D>::axis(k), P) * P.inv2V > 0.0;
+    return ok;
+  }
+  __device__ static double macro_entropy(const Node& c, const Phys&) { return 0.5 * c.u * c.u; }
+  template <int k>
+  __device__ static bool bregman(const Node&, const double*, const double* e, double& B, double* dv, const Phys& P) {
+    const double wk = P.w + Lat<D>::sign(k) * a(Lat<D>::axis(k), P) * P.inv2V;
+    const double dU = e[0] / wk;
+    B = 0.5 * wk * dU * dU;
+    dv[0] = dU;
+    return wk > 0.0;
+  }
+};
+
+// ---------------------------------------------------------------- Burgers
+// phi^j = b_j u^2 / 2, S = u^2/2, s_k^*(p) = w p^2/2 + beta_k p^3 / (12V),
+// beta_k = sigma_k b_{n_k} (Example "Burgers' equation"; Sec. 3.3 in 2D).
+// Increment equation of the population state: (beta/4V) dU^2 + c1 dU - e = 0,
+// c1 = w + beta u / (2V); B = dU^2 (w/2 + beta (3u + 2 dU) / (12V)).
+template <int D> struct Burgers {
+  static constexpr int M = 1, Q = Lat<D>::Q;
+  struct Node { double u; };
+  __device__ static double b(int j, const Phys& P) { return j == 0 ? P.p0 : P.p1; }
+  __device__ static void flux(const double* u, int j, double* phi, const Phys& P) { phi[0] = 0.5 * b(j, P) * u[0] * u[0]; }
+  __device__ static bool prepare(const double* u, Node& c, const Phys&) { c.u = u[0]; return true; }
+  __device__ static bool subchar(const Node& c, const Phys& P) {
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) ok &= P.w + Lat<D>::sign(k) * b(Lat<D>::axis(k), P) * c.u * P.inv2V > 0.0;
+    return ok;
+  }
+  __device__ static double macro_entropy(const Node& c, const Phys&) { return 0.5 * c.u * c.u; }
+  template <int k>
+  __device__ static bool bregman(const Node& c, const double*, const double* e, double& B, double* dv, const Phys& P) {
+    const double beta = Lat<D>::sign(k) * b(Lat<D>::axis(k), P);
+    const double c1 = P.w + beta * c.u * P.inv2V;
+    const double disc = c1 * c1 + 2.0 * beta * e[0] * P.inv2V;
+    const bool ok = (c1 > 0.0) && (disc > 0.0);
+    const double dU = 2.0 * e[0] / (c1 + sqrt(ok ? disc : c1 * c1));
+    B = dU * dU * (0.5 * P.w + beta * (3.0 * c.u + 2.0 * dU) * (P.inv2V * (1.0 / 6.0)));
+    dv[0] = dU;
+    return ok;
+  }
+};
+
+// ---------------------------------------------------------------- shallow water
+// u = (h, h u_1..u_D), S = h|u|^2/2 + g h^2/2, v = (g h - |u|^2/2, u)
+// (Example "Shallow water system"; D2Q4 by the same construction).  For
+// velocity k (axis n, sign sigma), W = 2wV + sigma u_n:
+//   f^eq_1 = h W / (2V), f^eq_n = f^eq_1 u_n + sigma g h^2 / (4V), f^eq_t = f^eq_1 u_t,
+//   s_k^* = g h^2 W / (4V).
+// Increment equation for dn = u'_n - u_n (x = f^eq + e, x_1 = f^eq_1 + e_1,
+// g_n = e_n - e_1 u_n, W' = W + sigma dn):
+//   sigma g V (sigma dn f^eq_1 - e_1 W)(f^eq_1 W' + x_1 W) + (g_n - x_1 dn) W^2 W'^2 = 0,
+// the cubic of the example with its O(1) part cancelled exactly; Newton from
+// dn = 0 follows the branch with W'^2 > g h' (the physical one).  Then
+//   du_t = (e_t - u_t e_1) / x_1,  dh = 2V (e_1 W - sigma f^eq_1 dn) / (W W'),
+//   B = [g W dh^2 + 2 sigma g h' dh dn + h' W' |du|^2] / (4V).
+template <int D> struct ShallowWater {
+  static constexpr int M = D + 1, Q = Lat<D>::Q;
+  struct Node { double h, vel[D]; };
+  __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
+    const double h = u[0];
+    const double uj = u[1 + j] / h;
+    phi[0] = u[1 + j];
+#pragma unroll
+    for (int i = 0; i < D; ++i) phi[1 + i] = u[1 + i] * uj;
+    phi[1 + j] += 0.5 * P.p0 * h * h;
+  }
+  __device__ static bool prepare(const double* u, Node& c, const Phys&) {
+    c.h = u[0];
+    const double ih = 1.0 / u[0];
+#pragma unroll
+    for (int i = 0; i < D; ++i) c.vel[i] = u[1 + i] * ih;
+    return u[0] > 0.0;
+  }
+  __device__ static bool subchar(const Node& c, const Phys& P) {
+    bool ok = c.h > 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const double W = P.W0 + Lat<D>::sign(k) * c.vel[Lat<D>::axis(k)];
+      ok &= (W > 0.0) && (W * W > P.p0 * c.h);
+    }
+    return ok;
+  }
+  __device__ static double macro_entropy(const Node& c, const Phys& P) {
+    double v2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) v2 += c.vel[i] * c.vel[i];
+    return 0.5 * c.h * v2 + 0.5 * P.p0 * c.h * c.h;
+  }
+  template <int k>
+  __device__ static bool bregman(const Node& c, const double* feq, const double* e, double& B, double* dv,
+                                 const Phys& P) {
+    constexpr int n = Lat<D>::axis(k);
+    constexpr double s = Lat<D>::sign(k);
+    const double g = P.p0, V = P.V;
+    const double un = c.vel[n];
+    const double W = P.W0 + s * un;
+    const double f1 = feq[0], e1 = e[0];
+    const double x1 = f1 + e1;
+    const double gn = e[1 + n] - e1 * un;
+    const double W2 = W * W;
+    double dn = 0.0;
+#pragma unroll 1
+    for (int it = 0; it < 30; ++it) {
+      const double Wp = W + s * dn;
+      const double A = s * dn * f1 - e1 * W;
+      const double Bq = f1 * Wp + x1 * W;
+      const double C = gn - x1 * dn;
+      const double Dq = W2 * Wp * Wp;
+      const double Pv = s * g * V * A * Bq + C * Dq;
+      const double dP = g * V * f1 * (Bq + A) - x1 * Dq + 2.0 * s * C * W2 * Wp;
+      const double st = Pv / dP;
+      dn -= st;
+      if (!(fabs(st) > 0x1p-51 * fabs(dn))) break;
+    }
+    const double Wp = W + s * dn;
+    const double dh = 2.0 * V * (e1 * W - s * f1 * dn) / (W * Wp);
+    const double hp = c.h + dh;
+    double du2 = dn * dn;
+    double kin = dn * (2.0 * un + dn);
+    dv[1 + n] = dn;
+    if (D == 2) {
+      constexpr int t = 1 - n;
+      const double ut = c.vel[t];
+      const double dt = (e[1 + t] - ut * e1) / x1;
+      du2 += dt * dt;
+      kin += dt * (2.0 * ut + dt);
+      dv[1 + t] = dt;
+    }
+    B = (g * W * dh * dh + 2.0 * s * g * hp * dh * dn + hp * Wp * du2) * (0.5 * P.inv2V);
+    dv[0] = g * dh - 0.5 * kin;
+    return (x1 > 0.0) && (Wp > 0.0) && (hp > 0.0) && (Wp * Wp > g * hp) && isfinite(B);
+  }
+};
+
+// ---------------------------------------------------------------- Euler (D2Q4)
+// u = (rho, rho u, rho v, E), p = (gamma-1)(E - rho|u|^2/2) (Sec. 6.3).  Entropy
+// S = -rho s/(gamma-1), s = ln p - gamma ln rho, v = ((gamma-s)/(gamma-1) -
+// beta|u|^2/2, beta u, -beta), beta = rho/p; s_k^* is the mass component of
+// f_k^eq.  For velocity k (axis n, sign sigma), W = 2wV + sigma u_n:
+//   x_1 = rho W/(2V), x_n = x_1 u_n + sigma p/(2V), x_t = x_1 u_t,
+//   x_E = (E W + sigma u_n p)/(2V).
+// Increments: du_t = (e_t - u_t e_1)/x_1, dp = 2 sigma V (g_n - x_1 dn),
+// drho = 2V (e_1 W - sigma f^eq_1 dn)/(W W'), and dn solves a A dn^2 + b dn + c = 0
+// (energy relation, O(1) part removed); the root continuous from dn = 0 is the
+// physical branch (rho' W'^2 > gamma p').  With al = dp/p, be = drho/rho and
+// ds = log1p(al) - gamma log1p(be):
+//   B = x_1 [((al - be)/(1+be) - ds)/(gamma-1) - be/(1+be)]
+//       + rho x_1 |du|^2 / (2p) + sigma rho dp dn / (2V p).
+struct Euler2 {
+  static constexpr int D = 2, M = 4, Q = 4;
+  struct Node { double rho, vel[2], p, E; };
+  __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
+    const double rho = u[0], ir = 1.0 / rho;
+    const double vx = u[1] * ir, vy = u[2] * ir;
+    const double p = (P.p0 - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
+    const double uj = j == 0 ? vx : vy;
+    phi[0] = u[1 + j];
+    phi[1] = u[1] * uj;
+    phi[2] = u[2] * uj;
+    phi[1 + j] += p;
+    phi[3] = uj * (u[3] + p);
+  }
+  __device__ static bool prepare(const double* u, Node& c, const Phys& P) {
+    c.rho = u[0];
+    const double ir = 1.0 / u[0];
+    c.vel[0] = u[1] * ir;
+    c.vel[1] = u[2] * ir;
+    c.E = u[3];
+    c.p = (P.p0 - 1.0) * (u[3] - 0.5 * u[0] * (c.vel[0] * c.vel[0] + c.vel[1] * c.vel[1]));
+    return (c.rho > 0.0) && (c.p > 0.0);
+  }
+  __device__ static bool subchar(const Node& c, const Phys& P) {
+    if (!((c.rho > 0.0) && (c.p > 0.0))) return false;
+    const double cs2 = P.p0 * c.p / c.rho;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double W = P.W0 + Lat<2>::sign(k) * c.vel[Lat<2>::axis(k)];
+      ok &= (W > 0.0) && (W * W > cs2);
+    }
+    return ok;
+  }
+  __device__ static double macro_entropy(const Node& c, const Phys& P) {
+    return -c.rho * (log(c.p) - P.p0 * log(c.rho)) / (P.p0 - 1.0);
+  }
+  template <int k>
+  __device__ static bool bregman(const Node& c, const double* feq, const double* e, double& B, double* dv,
+                                 const Phys& P) {
+    constexpr int n = Lat<2>::axis(k), t = 1 - n;
+    constexpr double s = Lat<2>::sign(k);
+    const double gm = P.p0, gm1 = P.p0 - 1.0, igm1 = 1.0 / gm1, V = P.V;
+    const double rho = c.rho, p = c.p, un = c.vel[n], ut = c.vel[t];
+    const double W = P.W0 + s * un;
+    const double f1 = feq[0], e1 = e[0];
+    const double x1 = f1 + e1;
+    const double ix1 = 1.0 / x1;
+    const double gn = e[1 + n] - e1 * un;
+    const double dt = (e[1 + t] - ut * e1) * ix1;
+    const double utp = ut + dt;
+    const double P0 = 2.0 * V * s * gn;
+    const double P1 = -2.0 * V * s * x1;
+    const double qa = -V * x1 * (gm + 1.0) * igm1;
+    const double qb = 2.0 * V * x1 * un + (s * P0 + P1 * W + s * p) * igm1 + s * p + s * P0 + s * un * P1;
+    const double qc = -2.0 * V * e[3] + V * (e1 * (un * un + utp * utp) + f1 * dt * (2.0 * ut + dt)) +
+                      P0 * W * igm1 + s * un * P0;
+    const double disc = qb * qb - 4.0 * qa * qc;
+    const bool okd = disc >= 0.0;
+    const double den = qb + copysign(sqrt(okd ? disc : 0.0), qb);
+    const double dn = -2.0 * qc / den;
+    const double dp = P0 + P1 * dn;
+    const double Wp = W + s * dn;
+    const double drho = 2.0 * V * (e1 * W - s * f1 * dn) / (W * Wp);
+    const double rhop = rho + drho, pp = p + dp;
+    const double ip = 1.0 / p;
+    const double al = dp * ip, be = drho / rho;
+    const double ibb = 1.0 / (1.0 + be);
+    const double ds = log1p(al) - gm * log1p(be);
+    const double du2 = dn * dn + dt * dt;
+    B = x1 * (((al - be) * ibb - ds) * igm1 - be * ibb) + 0.5 * rho * x1 * du2 * ip + s * rho * dp * dn * ip * P.inv2V;
+    // entropy-variable difference v(U_k) - v(u)
+    const double bet = rho * ip;
+    const double dbet = bet * (be - al) / (1.0 + al);
+    const double unp = un + dn;
+    const double up2 = unp * unp + utp * utp;
+    const double dkin = dbet * up2 + bet * (dn * (2.0 * un + dn) + dt * (2.0 * ut + dt));
+    dv[0] = -ds * igm1 - 0.5 * dkin;
+    dv[1 + n] = dbet * unp + bet * dn;
+    dv[1 + t] = dbet * utp + bet * dt;
+    dv[3] = -dbet;
+    return okd && (x1 > 0.0) && (Wp > 0.0) && (rhop > 0.0) && (pp > 0.0) && (rhop * Wp * Wp > gm * pp) && isfinite(B);
+  }
+};
+
+// ------------------------------------------------------------- node relaxation
+
+template <class S> struct Eq {
+  static constexpr int Q = S::Q, M = S::M;
+  // f_k^eq(u) = w u + sigma_k phi^{n_k}(u) / (2V)
+  __device__ static void equilibrium(const double* u, double (&feq)[Q][M], const Phys& P) {
+    double phx[M], phy[M];
+    S::flux(u, 0, phx, P);
+    if (Q == 4) S::flux(u, 1, phy, P);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int ax = (Q == 4) ? (k & 1) : 0;
+      const double s = (k < Q / 2) ? P.inv2V : -P.inv2V;
+#pragma unroll
+      for (int m = 0; m < M; ++m) feq[k][m] = P.w * u[m] + s * (ax == 0 ? phx[m] : phy[m]);
+    }
+  }
+};
+
+// F(t) = sum_k B_k and F'(t) = sum_k (v(U_k) - v(u)) . d_k, velocities k..Q-1.
+template <class S, int k = 0>
+__device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&feq)[S::Q][S::M],
+                                     const double (&d)[S::Q][S::M], double t, double& F, double& dF, const Phys& P) {
+  if constexpr (k == S::Q) {
+    return true;
+  } else {
+    double e[S::M], dv[S::M], B;
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) e[m] = t * d[k][m];
+    const bool ok = S::template bregman<k>(c, feq[k], e, B, dv, P);
+    F += B;
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) dF += dv[m] * d[k][m];
+    const bool rest = fsum<S, k + 1>(c, feq, d, t, F, dF, P);
+    return ok && rest;
+  }
+}
+
+enum : unsigned { FLAG_INADMISSIBLE = 1u, FLAG_NAN = 2u, FLAG_FALLBACK = 4u, FLAG_SUBCHAR = 8u };
+
+// Relax one node in place.  mode 0: omega = P.omega; mode 1: entropy-limited
+// omega (safeguarded Newton on H(lambda) = F(-lambda) - F(1), bisection bracket,
+// stopped once a step no longer moves f^eq - lambda d beyond rounding).
+// Returns omega used; sets flags.
+template <class S>
+__device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags) {
+  constexpr int Q = S::Q, M = S::M;
+  double u[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double acc = f[0][m];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) acc += f[k][m];
+    u[m] = acc;
+  }
+  double feq[Q][M];
+  Eq<S>::equilibrium(u, feq, P);
+  if (mode == 0) {
+    const double om = P.omega, om1 = 1.0 - P.omega;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m) f[k][m] = om1 * f[k][m] + om * feq[k][m];
+    return om;
+  }
+  double d[Q][M];
+  double dmax = 0.0, fsc = 0.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      d[k][m] = f[k][m] - feq[k][m];
+      dmax = fmax(dmax, fabs(d[k][m]));
+      fsc = fmax(fsc, fmax(fabs(feq[k][m]), fabs(f[k][m])));
+    }
+  double lam = 1.0;
+  typename S::Node c;
+  const bool adm = S::prepare(u, c, P);
+  if (!adm) flags |= FLAG_INADMISSIBLE;
+  if (dmax == 0.0) return 2.0;  // at equilibrium: omega = 2 (limit of the root)
+  double F1 = 0.0, dF1 = 0.0;
+  bool ok1 = adm && fsum<S>(c, feq, d, 1.0, F1, dF1, P);
+  bool fallback = !ok1;
+  if (ok1 && F1 > 0.0) {
+    const double tol = 2.0 * 2.220446049250313e-16 * fsc;
+    double lo = 0.0, hi = INFINITY, x = 1.0;
+    bool hi_bad = false;
+#pragma unroll 1
+    for (int it = 0; it < 100; ++it) {
+      double F = 0.0, dF = 0.0;
+      const bool ok = fsum<S>(c, feq, d, -x, F, dF, P);
+      const double H = F - F1, dH = -dF;
+      if (ok && H == 0.0) { lam = x; break; }
+      const bool above = !ok || (H > 0.0);
+      if (above) {
+        if (x <= hi) { hi = x; hi_bad = !ok; }
+      } else {
+        lo = fmax(lo, x);
+      }
+      const double xn = x - H / dH;
+      const bool newton_ok = ok && isfinite(xn) && (xn > lo) && (xn < hi);
+      const double xnew = newton_ok ? xn : (isinf(hi) ? 2.0 * x : 0.5 * (lo + hi));
+      if (newton_ok && fabs(xnew - x) * dmax <= tol) { lam = xnew; break; }
+      if (!isinf(hi) && (hi - lo) * dmax <= tol) {
+        if (hi_bad) fallback = true; else lam = hi;
+        break;
+      }
+      x = xnew;
+      lam = x;
+    }
+  }
+  if (fallback) {
+    lam = 0.0;
+    flags |= FLAG_FALLBACK;
+  }
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[k][m] = feq[k][m] - lam * d[k][m];
+  return lam + 1.0;
+}
+
+}  // namespace eslb
