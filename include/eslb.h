@@ -161,6 +161,79 @@ int eslb_reset_counters(eslb_ctx* ctx);
 /* Synchronise the stream and return the sticky status. */
 int eslb_sync_status(eslb_ctx* ctx);
 
+/* ---------------------------------------------------------------- adjoint
+ * Reverse-mode derivative of the time loop (not in the paper: the derivative of
+ * its scheme).  One relaxation maps the stage input h to
+ * g = (1-omega) h + omega f^eq(sum h); its adjoint maps gbar to
+ *   hbar_j = (1-omega) gbar_j + omega sum_k J_k^T gbar_k
+ *            + grad_{h_j} omega * sum_k (f^eq_k - h_k) . gbar_k,
+ * with grad omega from the implicit function theorem on eq. variableOmegaProblem
+ * (zero term for fixed omega).  The adjoint of a transport T(s) is T(-s), which
+ * is offset bookkeeping only. */
+
+/* Adjoint of one eslb_relax pass at the current offsets: h_dev is the pass input
+ * (q*M planes, storage layout, read), gbar_dev the cotangent of its output in the
+ * same storage layout, overwritten with the cotangent of h.  Must not alias.
+ * Asynchronous. */
+int eslb_relax_adjoint(eslb_ctx* ctx, const double* h_dev, double* gbar_dev);
+/* Adjoint of eslb_moments: fbar_k = ubar for every k (logical layout, offsets 0).
+ * ubar_dev: M planes (read); fbar_dev: q*M planes (written).  Asynchronous. */
+int eslb_moments_adjoint(eslb_ctx* ctx, const double* ubar_dev, double* fbar_dev);
+/* Adjoint of eslb_init_equilibrium: ubar = sum_k (d f_k^eq / du)(u)^T fbar_k.
+ * u_dev, ubar_dev: M planes; fbar_dev: q*M planes, logical layout.  Asynchronous. */
+int eslb_init_adjoint(eslb_ctx* ctx, const double* u_dev, const double* fbar_dev, double* ubar_dev);
+/* Device bytes eslb_adjoint needs for (nsteps, ckpt_every):
+ * (ceil(nsteps/ckpt_every) + ckpt_every + passes_per_step + 2) states. */
+int eslb_adjoint_workspace_bytes(const eslb_ctx* ctx, int64_t nsteps, int64_t ckpt_every, size_t* bytes);
+/* Cotangent of the initial distributions through nsteps composed steps.
+ * f0_dev: the forward initial state in storage layout with the context's current
+ * offsets (read only).  fbar_dev: on entry the cotangent of the state after
+ * nsteps steps, on return the cotangent of f0; both in logical layout (offsets
+ * applied, as eslb_gather returns).  work_dev: caller-owned device workspace of at
+ * least eslb_adjoint_workspace_bytes bytes.  Checkpoints every ckpt_every steps,
+ * recomputes each segment's step states and each step's stage inputs, then runs
+ * the adjoint passes in reverse.  The context's offsets are unchanged on return.
+ * Asynchronous. */
+int eslb_adjoint(eslb_ctx* ctx, const double* f0_dev, int64_t nsteps, int64_t ckpt_every, double* fbar_dev,
+                 void* work_dev, size_t work_bytes);
+
+/* ---------------------------------------------------------------- batched ensembles
+ * Many independent problems of one kind (same lattice, system, relax mode, scheme
+ * and kappa; grid sizes, V, dx and system parameters may differ) advanced by one
+ * persistent stage kernel over a device table of tiles of every active instance,
+ * all instances in lockstep through the same composed-step schedule; the passes
+ * of a few steps are captured in one hipGraph whose replays need no host work.
+ * Not a method of the paper: an execution pattern for many problems at once; each
+ * instance is computed exactly as eslb_step computes it. */
+typedef struct eslb_batch eslb_batch;
+
+/* probs: n problem statements (copied).  Every instance starts with offsets 0.
+ * stream: the caller's stream (work is ordered after what is queued on it). */
+int eslb_batch_create(const eslb_problem* probs, int32_t n, void* stream, eslb_batch** out);
+void eslb_batch_destroy(eslb_batch* batch);
+/* Advance instance i by nsteps[i] >= 0 composed steps, in place.  f_devs[i]: its
+ * state (q*M planes of nx_i*ny_i, storage layout with the instance's offsets; may
+ * be NULL when nsteps[i] == 0).  Synchronises with the batch's own stream before
+ * returning (the caller's stream is made to wait for it as well). */
+int eslb_batch_run(eslb_batch* batch, double* const* f_devs, const int64_t* nsteps);
+/* Offsets of instance i (q entries, all equal: transport moves every velocity by
+ * the same number of cells). */
+int eslb_batch_get_offsets(const eslb_batch* batch, int32_t i, int64_t* offsets);
+int eslb_batch_set_offsets(eslb_batch* batch, int32_t i, const int64_t* offsets);
+/* Synchronise and return the sticky status of the whole batch. */
+int eslb_batch_sync_status(eslb_batch* batch);
+/* Launch configuration: tile block_x x block_y (64x4, 64x2, 128x2, 256x1, 32x8),
+ * persistent blocks per compute unit, composed steps per captured graph. */
+int eslb_batch_set_config(eslb_batch* batch, int32_t block_x, int32_t block_y, int32_t blocks_per_cu,
+                          int32_t steps_per_graph);
+int eslb_batch_get_config(const eslb_batch* batch, int32_t* cfg4);
+/* Autotuner: times every supported configuration on scratch copies of one
+ * instance per distinct grid size (trial_steps steps each; allocates and frees
+ * the copies) and keeps the fastest; *best_ms (optional) gets its trial time.
+ * The caller's states and offsets are not modified. */
+int eslb_batch_autotune(eslb_batch* batch, double* const* f_devs, int32_t trial_steps, double* best_ms);
+const char* eslb_batch_last_error(const eslb_batch* batch);
+
 const char* eslb_status_string(int code);
 const char* eslb_last_error(const eslb_ctx* ctx);
 

@@ -46,7 +46,7 @@ def eq_jacobian_T(lat, sys, V, u, y):
 def _dv_all(lat, sys, V, u, feq, d, t):
     dvs = []
     for k in range(lat.q):
-        _, dv, _ = sys.bregman(lat, V, k, u, feq[k] + t * d[k])
+        _, dv, _ = sys.bregman(lat, V, k, u, feq[k], t * d[k])
         dvs.append(dv)
     return np.array(dvs)
 

@@ -28,8 +28,12 @@ s_k(x) = v(U_k).x - s_k^*(v(U_k)) with v = grad S.  The Bregman divergence
     B_k(x) = s_k(x) - s_k(f_k^eq(u)) - v(u).(x - f_k^eq(u))
 is written below in closed form as a quadratic-type expression of the state
 differences U_k - u, which keeps it accurate when x is close to equilibrium
-(the paper's "factorise the distance from equilibrium", Sec. 5.1).
-The closed forms are pinned against 50-digit brute force in the tests.
+(the paper's "factorise the distance from equilibrium", Sec. 5.1).  The
+differences themselves are solved from the increment e = x - f_k^eq(u): the
+equation f_k^eq(u + dU) - f_k^eq(u) = e has its O(1) part cancelled exactly, so
+dU carries a relative (not absolute) rounding error; the plain inversion
+(population_state) picks the branch and is pinned against numpy.roots.
+The closed forms are pinned against 40-digit brute force in the tests.
 """
 import numpy as np
 
@@ -69,11 +73,11 @@ class Advection:
     def _wk(self, lat, V, k):
         return lat.w + lat.sign[k] * self.a[lat.axis[k]] / (2.0 * V)
 
-    def bregman(self, lat, V, k, u, x):
-        """s_k(x) = x^2 / (2 w_k), w_k = w + sigma a_n / (2V): B = w_k (U_k - u)^2 / 2."""
+    def bregman(self, lat, V, k, u, feqk, e):
+        """s_k(x) = x^2 / (2 w_k), w_k = w + sigma a_n / (2V): w_k dU = e, B = w_k dU^2 / 2."""
         wk = self._wk(lat, V, k)
         with np.errstate(divide="ignore", invalid="ignore"):
-            dU = x[0] / wk - u[0]
+            dU = e[0] / wk
         B = 0.5 * wk * dU ** 2
         valid = np.full(dU.shape, wk > 0)
         return B, dU[None], valid
@@ -115,11 +119,18 @@ class Burgers:
         U = 2.0 * x / (lat.w + np.sqrt(np.where(valid, disc, 1.0)))
         return U, valid
 
-    def bregman(self, lat, V, k, u, x):
-        """B_k = dU^2 [w/2 + beta (3u + 2 dU) / (12V)], dU = U_k - u (Taylor of the cubic s_k^*)."""
+    def bregman(self, lat, V, k, u, feqk, e):
+        """B_k = dU^2 [w/2 + beta (3u + 2 dU) / (12V)], dU = U_k - u (Taylor of the cubic s_k^*).
+
+        Increment form: f_k^eq(u + dU) - f_k^eq(u) = e reads (beta/4V) dU^2 + c1 dU = e,
+        c1 = w + beta u / (2V), solved as dU = 2e / (c1 + sqrt(c1^2 + beta e / V)); the
+        convex branch needs c1 > 0 (sub-characteristic) and a positive discriminant.
+        """
         beta = lat.sign[k] * self.b[lat.axis[k]]
-        U, valid = self.population_state(lat, V, k, x[0])
-        dU = U - u[0]
+        c1 = lat.w + beta * u[0] / (2.0 * V)
+        disc = c1 ** 2 + beta * e[0] / V
+        valid = (c1 > 0) & (disc > 0)
+        dU = 2.0 * e[0] / (c1 + np.sqrt(np.where(valid, disc, c1 ** 2)))
         B = dU ** 2 * (0.5 * lat.w + beta * (3.0 * u[0] + 2.0 * dU) / (12.0 * V))
         return B, dU[None], valid
 
@@ -223,21 +234,46 @@ class ShallowWater:
             vel.append(z if j == n else x[1 + j] / np.where(valid, x1, 1.0))
         return h, np.array(vel), valid
 
-    def bregman(self, lat, V, k, u, x):
+    def bregman(self, lat, V, k, u, feqk, e):
         """B_k = [g W dh^2 + 2 sigma g h' dh du_n + h' W' |du|^2] / (4V).
 
         dh = h' - h, du = u' - u (population state minus cell state); W and W' are
         2wV + sigma u_n at the cell and at the population state.  Derived from the
         Legendre form of B_k with s_k^* = g h^2 W / (4V); pinned by brute force.
+        The offsets come from the increment form of the inversion: with
+        x_1 = f_1 + e_1, g_n = e_n - e_1 u_n and W' = W + sigma dn,
+            sigma g V (sigma dn f_1 - e_1 W)(f_1 W' + x_1 W) + (g_n - x_1 dn) W^2 W'^2 = 0
+        (the cubic of the example minus its value at the cell state), refined by
+        Newton from the root of the plain cubic; then du_t = (e_t - u_t e_1) / x_1
+        and dh = 2V (e_1 W - sigma f_1 dn) / (W W').
         """
         n, s, g = lat.axis[k], lat.sign[k], self.g
         h = u[0]
         vel = u[1:] / h
-        hp, velp, valid = self.population_state(lat, V, k, x)
-        dh = hp - h
-        du = velp - vel
+        x = feqk + e
+        hp0, velp0, valid = self.population_state(lat, V, k, x)
         W = 2.0 * lat.w * V + s * vel[n]
-        Wp = 2.0 * lat.w * V + s * velp[n]
+        f1, e1 = feqk[0], e[0]
+        x1 = f1 + e1
+        gn = e[1 + n] - e1 * vel[n]
+        dn = np.where(valid, velp0[n] - vel[n], 0.0)
+        for _ in range(3):
+            Wp = W + s * dn
+            A = s * dn * f1 - e1 * W
+            Bq = f1 * Wp + x1 * W
+            C = gn - x1 * dn
+            Dq = W ** 2 * Wp ** 2
+            P = s * g * V * A * Bq + C * Dq
+            dP = g * V * f1 * (Bq + A) - x1 * Dq + 2.0 * s * C * W ** 2 * Wp
+            dn = dn - np.where(valid & (dP != 0), P / np.where(dP == 0, 1.0, dP), 0.0)
+        Wp = W + s * dn
+        dh = 2.0 * V * (e1 * W - s * f1 * dn) / (W * np.where(valid, Wp, 1.0))
+        hp = h + dh
+        du = []
+        x1s = np.where(valid, x1, 1.0)
+        for j in range(self.d):
+            du.append(dn if j == n else (e[1 + j] - vel[j] * e1) / x1s)
+        du = np.array(du)
         du2 = np.sum(du ** 2, axis=0)
         B = (g * W * dh ** 2 + 2.0 * s * g * hp * dh * du[n] + hp * Wp * du2) / (4.0 * V)
         dv = np.concatenate([(g * dh - 0.5 * np.sum(du * (2.0 * vel + du), axis=0))[None], du])
@@ -345,33 +381,74 @@ class Euler:
             vel.append(z if j == n else x[1 + j] / x1s)
         return rho, np.array(vel), p, valid
 
-    def bregman(self, lat, V, k, u, x):
+    def bregman(self, lat, V, k, u, feqk, e):
         """B_k = x_1 [phi(a/b)/(gamma-1) + phi(1/b)] + rho x_1 |du|^2 / (2p) + sigma rho dp du_n / (2Vp).
 
         a = p'/p, b = rho'/rho, phi(z) = z - 1 - ln z, primes for the population
         state.  Derived from s_k(x) = -x_1 s(U_k) / (gamma-1); pinned by brute force.
+        Offsets in increment form (x = f^eq + e, x_1 = f_1 + e_1, g_n = e_n - e_1 u_n):
+            du_t = (e_t - u_t e_1) / x_1,   dp = 2 sigma V (g_n - x_1 dn),
+            drho = 2V (e_1 W - sigma f_1 dn) / (W W'),
+        and dn is the root near 0 of  qa dn^2 + qb dn + qc = 0, the energy relation
+        minus its value at the cell state:
+            qa = -V x_1 (gamma+1)/(gamma-1),
+            qb = 2V x_1 u_n + (sigma P0 + P1 W + sigma p)/(gamma-1) + sigma (p + P0 + u_n P1),
+            qc = -2V e_E + V [e_1 (u_n^2 + u_t'^2) + f_1 du_t (2 u_t + du_t)]
+                 + P0 W/(gamma-1) + sigma u_n P0,
+        P0 = 2 sigma V g_n, P1 = -2 sigma V x_1.  The plain inversion (population_state)
+        decides validity and the branch; the increment form gives the offsets.
         """
         n, s, gm = lat.axis[k], lat.sign[k], self.gamma
         rho, vel, p = self.primitives(u)
-        rp, velp, pp, valid = self.population_state(lat, V, k, x)
-        rps = np.where(valid, rp, rho)
-        pps = np.where(valid, pp, p)
-        a = pps / p
-        b = rps / rho
-        du = velp - vel
-        dp = pps - p
-        x1 = x[0]
-        B = (x1 * (_phi_log(a / b) / (gm - 1.0) + _phi_log(1.0 / b))
-             + rho * x1 * np.sum(du ** 2, axis=0) / (2.0 * p)
-             + s * rho * dp * du[n] / (2.0 * V * p))
-        # entropy-variable difference v(U_k) - v(u)
-        beta = rho / p
-        betap = rps / pps
-        dbeta = betap - beta
-        ds = np.log(a) - gm * np.log(b)
-        dv1 = -ds / (gm - 1.0) - 0.5 * (betap * np.sum(velp ** 2, axis=0) - beta * np.sum(vel ** 2, axis=0))
-        dv = np.concatenate([dv1[None], betap * velp - beta * vel, -dbeta[None]])
-        return B, dv, valid
+        x = feqk + e
+        _, _, _, valid = self.population_state(lat, V, k, x)
+        W0 = 2.0 * lat.w * V
+        un = vel[n]
+        W = W0 + s * un
+        f1, e1 = feqk[0], e[0]
+        x1 = f1 + e1
+        x1s = np.where(valid, x1, 1.0)
+        gn = e[1 + n] - e1 * un
+        du = [None] * self.d
+        ut2p = np.zeros_like(x1)
+        corr = np.zeros_like(x1)
+        for j in range(self.d):
+            if j != n:
+                du[j] = (e[1 + j] - vel[j] * e1) / x1s
+                ut2p = ut2p + (vel[j] + du[j]) ** 2
+                corr = corr + f1 * du[j] * (2.0 * vel[j] + du[j])
+        P0 = 2.0 * V * s * gn
+        P1 = -2.0 * V * s * x1
+        qa = -V * x1 * (gm + 1.0) / (gm - 1.0)
+        qb = 2.0 * V * x1 * un + (s * P0 + P1 * W + s * p) / (gm - 1.0) + s * (p + P0 + un * P1)
+        qc = -2.0 * V * e[1 + self.d] + V * (e1 * (un ** 2 + ut2p) + corr) + P0 * W / (gm - 1.0) + s * un * P0
+        disc = qb * qb - 4.0 * qa * qc
+        valid = valid & (disc >= 0)
+        den = qb + np.where(qb >= 0, 1.0, -1.0) * np.sqrt(np.where(valid, disc, 0.0))
+        dn = np.where(valid, -2.0 * qc / np.where(den == 0, 1.0, den), 0.0)
+        du[n] = dn
+        du = np.array(du)
+        dp = P0 + P1 * dn
+        Wp = W + s * dn
+        drho = 2.0 * V * (e1 * W - s * f1 * dn) / (W * np.where(valid, Wp, 1.0))
+        al = dp / p
+        be = drho / rho
+        zeta1 = (al - be) / (1.0 + be)          # a/b - 1
+        zeta2 = -be / (1.0 + be)                # 1/b - 1
+        with np.errstate(invalid="ignore", divide="ignore"):
+            phi1 = zeta1 - np.log1p(zeta1)
+            phi2 = zeta2 - np.log1p(zeta2)
+            B = (x1 * (phi1 / (gm - 1.0) + phi2) + rho * x1 * np.sum(du ** 2, axis=0) / (2.0 * p)
+                 + s * rho * dp * dn / (2.0 * V * p))
+            # entropy-variable difference v(U_k) - v(u)
+            beta = rho / p
+            dbeta = beta * (be - al) / (1.0 + al)
+            ds = np.log1p(al) - gm * np.log1p(be)
+        velp = vel + du
+        dkin = dbeta * np.sum(velp ** 2, axis=0) + beta * np.sum(du * (2.0 * vel + du), axis=0)
+        dv1 = -ds / (gm - 1.0) - 0.5 * dkin
+        dv = np.concatenate([dv1[None], dbeta * velp + beta * du, -dbeta[None]])
+        return np.where(valid, B, 0.0), dv, valid
 
     def admissible(self, u):
         rho, vel, p = self.primitives(u)
@@ -397,8 +474,7 @@ def bregman_sum(lat, sys, V, u, feq, d, t):
     dF = np.zeros(u.shape[1:])
     ok = np.ones(u.shape[1:], bool)
     for k in range(lat.q):
-        x = feq[k] + t * d[k]
-        Bk, dvk, vk = sys.bregman(lat, V, k, u, x)
+        Bk, dvk, vk = sys.bregman(lat, V, k, u, feq[k], t * d[k])
         F = F + Bk
         dF = dF + np.sum(dvk * d[k], axis=0)
         ok &= vk

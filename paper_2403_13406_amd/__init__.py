@@ -6,4 +6,5 @@ is libeslb.so (hand-written HIP, C ABI in include/eslb.h); this package only
 marshals arguments.  Importing it does not load the library; the first Solver
 does, and raises if the library is missing (there is no CPU fallback).
 """
+from .batch import Batch  # noqa: F401
 from .solver import EslbError, Solver, make_problem  # noqa: F401

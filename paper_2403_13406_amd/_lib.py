@@ -4,7 +4,7 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libeslb.so")
+LIB_PATH = os.environ.get("ESLB_LIBRARY") or os.path.join(HERE, "libeslb.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "eslb.h")
 
 c_int32, c_int64, c_double, c_void_p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
@@ -50,6 +50,21 @@ _SIGNATURES = {
     "eslb_set_stats": (c_int32, [c_void_p, c_int32]),
     "eslb_reset_counters": (c_int32, [c_void_p]),
     "eslb_sync_status": (c_int32, [c_void_p]),
+    "eslb_relax_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "eslb_moments_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "eslb_init_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    "eslb_adjoint_workspace_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
+    "eslb_adjoint": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_void_p, ctypes.c_size_t]),
+    "eslb_batch_create": (c_int32, [P(Problem), c_int32, c_void_p, P(c_void_p)]),
+    "eslb_batch_destroy": (None, [c_void_p]),
+    "eslb_batch_run": (c_int32, [c_void_p, P(c_void_p), P(c_int64)]),
+    "eslb_batch_get_offsets": (c_int32, [c_void_p, c_int32, P(c_int64)]),
+    "eslb_batch_set_offsets": (c_int32, [c_void_p, c_int32, P(c_int64)]),
+    "eslb_batch_sync_status": (c_int32, [c_void_p]),
+    "eslb_batch_set_config": (c_int32, [c_void_p, c_int32, c_int32, c_int32, c_int32]),
+    "eslb_batch_get_config": (c_int32, [c_void_p, P(c_int32)]),
+    "eslb_batch_autotune": (c_int32, [c_void_p, P(c_void_p), c_int32, P(c_double)]),
+    "eslb_batch_last_error": (ctypes.c_char_p, [c_void_p]),
     "eslb_status_string": (ctypes.c_char_p, [c_int32]),
     "eslb_last_error": (ctypes.c_char_p, [c_void_p]),
 }

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libeslb.so")
-SOURCES = ["eslb.hip"]
+SOURCES = ["eslb.hip", "eslb_batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -42,6 +42,28 @@ void eslb_set_global_error(const std::string& msg);
 
 }  // namespace eslb
 
+struct eslb_ctx;
+
+namespace eslb {
+// shared host helpers (defined in eslb.hip)
+int validate_problem(const eslb_problem* p, std::string& why, int* kind, int* d, int* q, int* M);
+Phys make_phys(const eslb_problem& p, int q);
+long long net_shift(const eslb_ctx* c);
+}  // namespace eslb
+
+// Calls CALL(SystemType, D) for the system kind of a context.
+#define ESLB_DISPATCH_KIND(KIND, CALL)                 \
+  switch (KIND) {                                      \
+    case eslb::KIND_ADV1: CALL(eslb::Advection<1>, 1); break;    \
+    case eslb::KIND_ADV2: CALL(eslb::Advection<2>, 2); break;    \
+    case eslb::KIND_BUR1: CALL(eslb::Burgers<1>, 1); break;      \
+    case eslb::KIND_BUR2: CALL(eslb::Burgers<2>, 2); break;      \
+    case eslb::KIND_SW1: CALL(eslb::ShallowWater<1>, 1); break;  \
+    case eslb::KIND_SW2: CALL(eslb::ShallowWater<2>, 2); break;  \
+    case eslb::KIND_EU2: CALL(eslb::Euler2, 2); break;           \
+    default: break;                                    \
+  }
+
 struct eslb_ctx {
   eslb_problem pb;
   int kind = 0, d = 1, q = 2, M = 1;

@@ -31,8 +31,33 @@ struct Phys {
   double w;      // 1 / q
   double W0;     // 2 w V
   double p0, p1; // system parameters (a_x,a_y | b_x,b_y | g | gamma)
+  double p2;     // derived: 1/(gamma-1) for Euler
   double omega;  // fixed relaxation parameter
 };
+
+// Reciprocal from the hardware estimate refined by two Newton steps
+// r <- r (2 - x r) (each squares the relative error; about 1 ulp at the end).
+// Arguments here are O(1) positive or negative normal numbers.
+__device__ __forceinline__ double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// log(1 + z).  For |z| < 1/64 (the increments near equilibrium) use
+// log(1+z) = 2 atanh(w), w = z / (2 + z), summed to w^9 (truncation below
+// 1e-19 relative); otherwise the library log1p.
+__device__ __forceinline__ double log1p_near0(double z) {
+  if (fabs(z) < 0.015625) {
+    const double w = z * rcp(2.0 + z);
+    const double w2 = w * w;
+    const double poly = fma(w2, fma(w2, fma(w2, fma(w2, 1.0 / 9.0, 1.0 / 7.0), 1.0 / 5.0), 1.0 / 3.0), 1.0);
+    return 2.0 * w * poly;
+  }
+  return log1p(z);
+}
 
 template <int D> struct Lat;
 template <> struct Lat<1> {
@@ -62,6 +87,8 @@ template <int D> struct Advection {
     return ok;
   }
   __device__ static double macro_entropy(const Node& c, const Phys&) { return 0.5 * c.u * c.u; }
+  // (d phi^j / du)^T z
+  __device__ static void fluxT(const Node&, int j, const double* z, double* out, const Phys& P) { out[0] = a(j, P) * z[0]; }
   template <int k>
   __device__ static bool bregman(const Node&, const double*, const double* e, double& B, double* dv, const Phys& P) {
     const double wk = P.w + Lat<D>::sign(k) * a(Lat<D>::axis(k), P) * P.inv2V;
@@ -90,6 +117,9 @@ template <int D> struct Burgers {
     return ok;
   }
   __device__ static double macro_entropy(const Node& c, const Phys&) { return 0.5 * c.u * c.u; }
+  __device__ static void fluxT(const Node& c, int j, const double* z, double* out, const Phys& P) {
+    out[0] = b(j, P) * c.u * z[0];
+  }
   template <int k>
   __device__ static bool bregman(const Node& c, const double*, const double* e, double& B, double* dv, const Phys& P) {
     const double beta = Lat<D>::sign(k) * b(Lat<D>::axis(k), P);
@@ -148,6 +178,16 @@ template <int D> struct ShallowWater {
 #pragma unroll
     for (int i = 0; i < D; ++i) v2 += c.vel[i] * c.vel[i];
     return 0.5 * c.h * v2 + 0.5 * P.p0 * c.h * c.h;
+  }
+  // phi^j = (m_j, m_i m_j / h + delta_ij g h^2 / 2): transposed Jacobian times z
+  __device__ static void fluxT(const Node& c, int j, const double* z, double* out, const Phys& P) {
+    double zv = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) zv += z[1 + i] * c.vel[i];
+    const double vj = c.vel[j];
+    out[0] = -vj * zv + P.p0 * c.h * z[1 + j];
+#pragma unroll
+    for (int l = 0; l < D; ++l) out[1 + l] = vj * z[1 + l] + (l == j ? z[0] + zv : 0.0);
   }
   template <int k>
   __device__ static bool bregman(const Node& c, const double* feq, const double* e, double& B, double* dv,
@@ -211,7 +251,7 @@ template <int D> struct ShallowWater {
 //       + rho x_1 |du|^2 / (2p) + sigma rho dp dn / (2V p).
 struct Euler2 {
   static constexpr int D = 2, M = 4, Q = 4;
-  struct Node { double rho, vel[2], p, E; };
+  struct Node { double rho, vel[2], p, E, irho, ip; };
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
     const double rho = u[0], ir = 1.0 / rho;
     const double vx = u[1] * ir, vy = u[2] * ir;
@@ -230,6 +270,8 @@ struct Euler2 {
     c.vel[1] = u[2] * ir;
     c.E = u[3];
     c.p = (P.p0 - 1.0) * (u[3] - 0.5 * u[0] * (c.vel[0] * c.vel[0] + c.vel[1] * c.vel[1]));
+    c.irho = ir;
+    c.ip = 1.0 / c.p;
     return (c.rho > 0.0) && (c.p > 0.0);
   }
   __device__ static bool subchar(const Node& c, const Phys& P) {
@@ -246,17 +288,30 @@ struct Euler2 {
   __device__ static double macro_entropy(const Node& c, const Phys& P) {
     return -c.rho * (log(c.p) - P.p0 * log(c.rho)) / (P.p0 - 1.0);
   }
+  // phi^j = (m_j, m_i vel_j + delta_ij p, vel_j (E + p)): transposed Jacobian times z
+  __device__ static void fluxT(const Node& c, int j, const double* z, double* out, const Phys& P) {
+    const double gm1 = P.p0 - 1.0;
+    const double vx = c.vel[0], vy = c.vel[1], vj = c.vel[j];
+    const double H = (c.E + c.p) / c.rho;
+    const double zv = z[1] * vx + z[2] * vy;
+    const double A = z[1 + j] + z[3] * vj;
+    const double dp_rho = 0.5 * gm1 * (vx * vx + vy * vy);
+    out[0] = -vj * zv + dp_rho * A - z[3] * vj * H;
+    out[1] = vj * z[1] - gm1 * vx * A + (j == 0 ? z[0] + zv + z[3] * H : 0.0);
+    out[2] = vj * z[2] - gm1 * vy * A + (j == 1 ? z[0] + zv + z[3] * H : 0.0);
+    out[3] = gm1 * z[1 + j] + P.p0 * vj * z[3];
+  }
   template <int k>
   __device__ static bool bregman(const Node& c, const double* feq, const double* e, double& B, double* dv,
                                  const Phys& P) {
     constexpr int n = Lat<2>::axis(k), t = 1 - n;
     constexpr double s = Lat<2>::sign(k);
-    const double gm = P.p0, gm1 = P.p0 - 1.0, igm1 = 1.0 / gm1, V = P.V;
+    const double gm = P.p0, igm1 = P.p2, V = P.V;
     const double rho = c.rho, p = c.p, un = c.vel[n], ut = c.vel[t];
     const double W = P.W0 + s * un;
     const double f1 = feq[0], e1 = e[0];
     const double x1 = f1 + e1;
-    const double ix1 = 1.0 / x1;
+    const double ix1 = rcp(x1);
     const double gn = e[1 + n] - e1 * un;
     const double dt = (e[1 + t] - ut * e1) * ix1;
     const double utp = ut + dt;
@@ -269,20 +324,20 @@ struct Euler2 {
     const double disc = qb * qb - 4.0 * qa * qc;
     const bool okd = disc >= 0.0;
     const double den = qb + copysign(sqrt(okd ? disc : 0.0), qb);
-    const double dn = -2.0 * qc / den;
+    const double dn = -2.0 * qc * rcp(den);
     const double dp = P0 + P1 * dn;
     const double Wp = W + s * dn;
-    const double drho = 2.0 * V * (e1 * W - s * f1 * dn) / (W * Wp);
+    const double drho = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
     const double rhop = rho + drho, pp = p + dp;
-    const double ip = 1.0 / p;
-    const double al = dp * ip, be = drho / rho;
-    const double ibb = 1.0 / (1.0 + be);
-    const double ds = log1p(al) - gm * log1p(be);
+    const double al = dp * c.ip, be = drho * c.irho;
+    const double ibb = rcp(1.0 + be);
+    const double ds = log1p_near0(al) - gm * log1p_near0(be);
     const double du2 = dn * dn + dt * dt;
-    B = x1 * (((al - be) * ibb - ds) * igm1 - be * ibb) + 0.5 * rho * x1 * du2 * ip + s * rho * dp * dn * ip * P.inv2V;
+    B = x1 * (((al - be) * ibb - ds) * igm1 - be * ibb) + 0.5 * rho * x1 * du2 * c.ip +
+        s * rho * dp * dn * c.ip * P.inv2V;
     // entropy-variable difference v(U_k) - v(u)
-    const double bet = rho * ip;
-    const double dbet = bet * (be - al) / (1.0 + al);
+    const double bet = rho * c.ip;
+    const double dbet = bet * (be - al) * rcp(1.0 + al);
     const double unp = un + dn;
     const double up2 = unp * unp + utp * utp;
     const double dkin = dbet * up2 + bet * (dn * (2.0 * un + dn) + dt * (2.0 * ut + dt));
@@ -332,16 +387,12 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&f
   }
 }
 
-enum : unsigned { FLAG_INADMISSIBLE = 1u, FLAG_NAN = 2u, FLAG_FALLBACK = 4u, FLAG_SUBCHAR = 8u };
-
-// Relax one node in place.  mode 0: omega = P.omega; mode 1: entropy-limited
-// omega (safeguarded Newton on H(lambda) = F(-lambda) - F(1), bisection bracket,
-// stopped once a step no longer moves f^eq - lambda d beyond rounding).
-// Returns omega used; sets flags.
+// u = sum_k f_k, f^eq(u), d = f - f^eq and the scales used by the stop rule.
 template <class S>
-__device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags) {
+__device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double (&u)[S::M],
+                                           double (&feq)[S::Q][S::M], double (&d)[S::Q][S::M], double& dmax,
+                                           double& fsc, const Phys& P) {
   constexpr int Q = S::Q, M = S::M;
-  double u[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     double acc = f[0][m];
@@ -349,18 +400,9 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
     for (int k = 1; k < Q; ++k) acc += f[k][m];
     u[m] = acc;
   }
-  double feq[Q][M];
   Eq<S>::equilibrium(u, feq, P);
-  if (mode == 0) {
-    const double om = P.omega, om1 = 1.0 - P.omega;
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-#pragma unroll
-      for (int m = 0; m < M; ++m) f[k][m] = om1 * f[k][m] + om * feq[k][m];
-    return om;
-  }
-  double d[Q][M];
-  double dmax = 0.0, fsc = 0.0;
+  dmax = 0.0;
+  fsc = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
 #pragma unroll
@@ -369,42 +411,101 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
       dmax = fmax(dmax, fabs(d[k][m]));
       fsc = fmax(fsc, fmax(fabs(feq[k][m]), fabs(f[k][m])));
     }
-  double lam = 1.0;
+}
+
+// lambda = omega - 1 solving F(-lambda) = F(1) (eq. variableOmegaProblem in the
+// Bregman form).  Safeguarded Newton on H(lambda) = F(-lambda) - F(1) with a
+// bisection bracket; after the samples at t = 1 and t = -1 the first move is taken
+// from the cubic Hermite model of G(t) = F(t)/t^2 on [-1, 1] (four values that the
+// two samples give for free), which is fourth-order accurate in the distance from
+// equilibrium, so one more sample usually ends the iteration.  Stops once a step
+// no longer moves f^eq - lambda d by more than rounding (2 eps * max|f|).
+// fallback = true when no root lies inside the convexity domain (omega = 1 then).
+template <class S>
+__device__ inline double entropic_lambda(const typename S::Node& c, const double (&feq)[S::Q][S::M],
+                                         const double (&d)[S::Q][S::M], double dmax, double fsc, const Phys& P,
+                                         bool& fallback) {
+  fallback = false;
+  double F1 = 0.0, dF1 = 0.0;
+  if (!fsum<S>(c, feq, d, 1.0, F1, dF1, P)) {
+    fallback = true;
+    return 0.0;
+  }
+  if (!(F1 > 0.0)) return 1.0;
+  const double tol = 2.0 * 2.220446049250313e-16 * fsc;
+  double lo = 0.0, hi = INFINITY, x = 1.0, lam = 1.0;
+  bool hi_bad = false;
+#pragma unroll 1
+  for (int it = 0; it < 100; ++it) {
+    double F = 0.0, dF = 0.0;
+    const bool ok = fsum<S>(c, feq, d, -x, F, dF, P);
+    const double H = F - F1, dH = -dF;
+    if (ok && H == 0.0) return x;
+    const bool above = !ok || (H > 0.0);
+    if (above) {
+      if (x <= hi) { hi = x; hi_bad = !ok; }
+    } else {
+      lo = fmax(lo, x);
+    }
+    double xn = x - H / dH;
+    if (it == 0 && ok) {
+      // cubic Hermite model of G on [-1, 1] from F(+-1), F'(+-1)
+      const double G1 = F1, Gm = F, G1p = dF1 - 2.0 * F1, Gmp = dF + 2.0 * F;
+      const double cc = 0.25 * (G1p - Gmp);
+      const double dd = 0.25 * ((G1p + Gmp) - (G1 - Gm));
+      const double bb = 0.5 * (G1 - Gm) - dd;
+      const double aa = 0.5 * (G1 + Gm) - cc;
+      double lp = 1.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double g = aa + lp * (-bb + lp * (cc - dd * lp));
+        const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
+        const double pv = lp * lp * g - G1;
+        const double pd = 2.0 * lp * g + lp * lp * gp;
+        lp -= pv / pd;
+      }
+      if (isfinite(lp) && lp > lo && lp < hi) xn = lp;
+    }
+    const bool newton_ok = ok && isfinite(xn) && (xn > lo) && (xn < hi);
+    const double xnew = newton_ok ? xn : (isinf(hi) ? 2.0 * x : 0.5 * (lo + hi));
+    if (newton_ok && fabs(xnew - x) * dmax <= tol) return xnew;
+    if (!isinf(hi) && (hi - lo) * dmax <= tol) {
+      if (hi_bad) {
+        fallback = true;
+        return 0.0;
+      }
+      return hi;
+    }
+    x = xnew;
+    lam = x;
+  }
+  return lam;
+}
+
+enum : unsigned { FLAG_INADMISSIBLE = 1u, FLAG_NAN = 2u, FLAG_FALLBACK = 4u, FLAG_SUBCHAR = 8u };
+
+// Relax one node in place.  mode 0: omega = P.omega (eq. relaxationDiscretizationOmega);
+// mode 1: entropy-limited omega (eq. variableOmegaProblem).  Returns omega used.
+template <class S>
+__device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags) {
+  constexpr int Q = S::Q, M = S::M;
+  double u[M], feq[Q][M], d[Q][M], dmax, fsc;
+  node_split<S>(f, u, feq, d, dmax, fsc, P);
+  if (mode == 0) {
+    const double om = P.omega, om1 = 1.0 - P.omega;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m) f[k][m] = om1 * f[k][m] + om * feq[k][m];
+    return om;
+  }
   typename S::Node c;
   const bool adm = S::prepare(u, c, P);
   if (!adm) flags |= FLAG_INADMISSIBLE;
   if (dmax == 0.0) return 2.0;  // at equilibrium: omega = 2 (limit of the root)
-  double F1 = 0.0, dF1 = 0.0;
-  bool ok1 = adm && fsum<S>(c, feq, d, 1.0, F1, dF1, P);
-  bool fallback = !ok1;
-  if (ok1 && F1 > 0.0) {
-    const double tol = 2.0 * 2.220446049250313e-16 * fsc;
-    double lo = 0.0, hi = INFINITY, x = 1.0;
-    bool hi_bad = false;
-#pragma unroll 1
-    for (int it = 0; it < 100; ++it) {
-      double F = 0.0, dF = 0.0;
-      const bool ok = fsum<S>(c, feq, d, -x, F, dF, P);
-      const double H = F - F1, dH = -dF;
-      if (ok && H == 0.0) { lam = x; break; }
-      const bool above = !ok || (H > 0.0);
-      if (above) {
-        if (x <= hi) { hi = x; hi_bad = !ok; }
-      } else {
-        lo = fmax(lo, x);
-      }
-      const double xn = x - H / dH;
-      const bool newton_ok = ok && isfinite(xn) && (xn > lo) && (xn < hi);
-      const double xnew = newton_ok ? xn : (isinf(hi) ? 2.0 * x : 0.5 * (lo + hi));
-      if (newton_ok && fabs(xnew - x) * dmax <= tol) { lam = xnew; break; }
-      if (!isinf(hi) && (hi - lo) * dmax <= tol) {
-        if (hi_bad) fallback = true; else lam = hi;
-        break;
-      }
-      x = xnew;
-      lam = x;
-    }
-  }
+  bool fallback = !adm;
+  double lam = 0.0;
+  if (adm) lam = entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback);
   if (fallback) {
     lam = 0.0;
     flags |= FLAG_FALLBACK;
@@ -414,6 +515,105 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
 #pragma unroll
     for (int m = 0; m < M; ++m) f[k][m] = feq[k][m] - lam * d[k][m];
   return lam + 1.0;
+}
+
+// sum_k J_k^T y_k, J_k = d f_k^eq / du = w I + sigma_k (d phi^{n_k}/du) / (2V).
+template <class S>
+__device__ __forceinline__ void eq_jacobian_T(const typename S::Node& c, const double (&y)[S::Q][S::M],
+                                              double (&out)[S::M], const Phys& P) {
+  constexpr int Q = S::Q, M = S::M;
+  double zx[M], zy[M], tx[M], ty[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    double a = y[0][m];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) a += y[k][m];
+    out[m] = P.w * a;
+    if (Q == 2) {
+      zx[m] = y[0][m] - y[1][m];
+    } else {
+      zx[m] = y[0][m] - y[2][m];
+      zy[m] = y[1][m] - y[3][m];
+    }
+  }
+  S::fluxT(c, 0, zx, tx, P);
+  if (Q == 4) S::fluxT(c, 1, zy, ty, P);
+#pragma unroll
+  for (int m = 0; m < M; ++m) out[m] += P.inv2V * (tx[m] + (Q == 4 ? ty[m] : 0.0));
+}
+
+template <class S, int k = 0>
+__device__ __forceinline__ void dv_all(const typename S::Node& c, const double (&feq)[S::Q][S::M],
+                                       const double (&d)[S::Q][S::M], double t, double (&dv)[S::Q][S::M],
+                                       const Phys& P) {
+  if constexpr (k < S::Q) {
+    double e[S::M], B;
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) e[m] = t * d[k][m];
+    (void)S::template bregman<k>(c, feq[k], e, B, dv[k], P);
+    dv_all<S, k + 1>(c, feq, d, t, dv, P);
+  }
+}
+
+// Adjoint of one relaxation at a node: gbar (cotangent of the output) becomes
+// hbar (cotangent of the input h), in place.
+//   hbar_j = (1-omega) gbar_j + omega sum_k J_k^T gbar_k + grad_{h_j} omega * c,
+//   c = sum_k (f^eq_k - h_k) . gbar_k,
+//   grad_{h_j} omega = [(1-omega) dv_j(-lambda) + omega sum_k J_k^T dv_k(-lambda) - dv_j(1)] / F'(-lambda),
+// dv_k(t) = v(U_k(t)) - v(u) (implicit function theorem on Sigma(R_omega h) = Sigma(h)).
+template <class S>
+__device__ inline void adjoint_node(const double (&h)[S::Q][S::M], double (&gb)[S::Q][S::M], int mode,
+                                    const Phys& P, unsigned& flags) {
+  constexpr int Q = S::Q, M = S::M;
+  double u[M], feq[Q][M], d[Q][M], dmax, fsc;
+  node_split<S>(h, u, feq, d, dmax, fsc, P);
+  typename S::Node c;
+  const bool adm = S::prepare(u, c, P);
+  double om = P.omega, lam = P.omega - 1.0;
+  bool grad = false;
+  if (mode == 1) {
+    if (!adm) flags |= FLAG_INADMISSIBLE;
+    if (dmax == 0.0) {
+      lam = 1.0;
+    } else {
+      bool fallback = !adm;
+      lam = adm ? entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback) : 0.0;
+      if (fallback) {
+        lam = 0.0;
+        flags |= FLAG_FALLBACK;
+      }
+      grad = !fallback;
+    }
+    om = lam + 1.0;
+  }
+  double JTg[M];
+  eq_jacobian_T<S>(c, gb, JTg, P);
+  if (grad) {
+    double dvm[Q][M], dv1[Q][M], JTdv[M];
+    dv_all<S>(c, feq, d, -lam, dvm, P);
+    dv_all<S>(c, feq, d, 1.0, dv1, P);
+    double Fp = 0.0, cc = 0.0;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        Fp += dvm[k][m] * d[k][m];
+        cc -= d[k][m] * gb[k][m];
+      }
+    eq_jacobian_T<S>(c, dvm, JTdv, P);
+    const double ratio = cc / Fp;
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        gb[k][m] = (1.0 - om) * gb[k][m] + om * JTg[m] +
+                   ((1.0 - om) * dvm[k][m] + om * JTdv[m] - dv1[k][m]) * ratio;
+  } else {
+#pragma unroll
+    for (int k = 0; k < Q; ++k)
+#pragma unroll
+      for (int m = 0; m < M; ++m) gb[k][m] = (1.0 - om) * gb[k][m] + om * JTg[m];
+  }
 }
 
 }  // namespace eslb

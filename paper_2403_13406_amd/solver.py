@@ -39,7 +39,7 @@ def make_problem(lattice, system, nx, ny=1, V=1.0, dx=None, kappa=1, relax="entr
     p.scheme = int(scheme)
     p.reserved = 0
     p.V = float(V)
-    p.dx = float(dx if dx is not None else 1.0 / nx)
+    p.dx = float(dx if dx is not None else (1.0 / nx if nx > 0 else 0.0))
     p.omega = float(omega)
     prm = list(param) + [0.0] * (4 - len(param))
     for i in range(4):
@@ -178,3 +178,40 @@ class Solver:
                 "macro_entropy": d.macro_entropy, "omega_min": d.omega_min, "omega_max": d.omega_max,
                 "n_fallback": d.n_fallback, "n_outside": d.n_outside, "n_inadmissible": d.n_inadmissible,
                 "n_nan": d.n_nan}
+
+    # -- adjoint
+    def relax_adjoint(self, h, gbar):
+        _check(self.lib, self.ctx, self.lib.eslb_relax_adjoint(self.ctx, self._ptr(h, self.state_shape),
+                                                               self._ptr(gbar, self.state_shape)))
+        return gbar
+
+    def moments_adjoint(self, ubar, fbar=None):
+        fbar = self.empty_state() if fbar is None else fbar
+        _check(self.lib, self.ctx, self.lib.eslb_moments_adjoint(self.ctx, self._ptr(ubar, self.moment_shape),
+                                                                 self._ptr(fbar, self.state_shape)))
+        return fbar
+
+    def init_adjoint(self, u, fbar, ubar=None):
+        import torch
+        ubar = torch.empty(self.moment_shape, dtype=torch.float64, device="cuda") if ubar is None else ubar
+        _check(self.lib, self.ctx, self.lib.eslb_init_adjoint(self.ctx, self._ptr(u, self.moment_shape),
+                                                              self._ptr(fbar, self.state_shape),
+                                                              self._ptr(ubar, self.moment_shape)))
+        return ubar
+
+    def adjoint_workspace_bytes(self, nsteps, ckpt_every):
+        b = ctypes.c_size_t()
+        _check(self.lib, self.ctx, self.lib.eslb_adjoint_workspace_bytes(self.ctx, int(nsteps), int(ckpt_every),
+                                                                         ctypes.byref(b)))
+        return b.value
+
+    def adjoint(self, f0, nsteps, ckpt_every, fbar, work=None):
+        """fbar (logical, cotangent of the state after nsteps) -> cotangent of f0, in place."""
+        import torch
+        nb = self.adjoint_workspace_bytes(nsteps, ckpt_every)
+        if work is None:
+            work = torch.empty(max(nb, 8), dtype=torch.uint8, device="cuda")
+        _check(self.lib, self.ctx, self.lib.eslb_adjoint(self.ctx, self._ptr(f0, self.state_shape), int(nsteps),
+                                                         int(ckpt_every), self._ptr(fbar, self.state_shape),
+                                                         ctypes.c_void_p(work.data_ptr()), work.numel()))
+        return fbar

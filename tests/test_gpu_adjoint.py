@@ -1,0 +1,111 @@
+"""Hand-written adjoint on the GPU against the CPU FP64 oracle adjoint and finite differences.
+
+Tolerances.  One adjoint pass on identical inputs: both sides evaluate the same
+expression with relative rounding, bar 1e-11 per conserved component (max-norm).
+Through several steps the two forward recomputations differ by rounding
+(~1e-16 relative), and the adjoint of the entropic relaxation depends on its
+input through grad omega, which is bounded but has a derivative of size 1/|d|
+(omega(f) is Lipschitz, not smooth, at equilibrium).  Nodes where d is tiny
+(extrema of smooth data) therefore amplify that rounding by ~1/|d|: the bar
+there is 1e-11 in the normwise L2 sense and 1e-9 in max-norm.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import componentwise_error, off_equilibrium, oracle_system, to_gpu, to_host
+from oracle.adjoint import adjoint_run, misfit_gradient, relax_adjoint
+from oracle.scheme import Relaxer, run
+from oracle.systems import equilibrium
+from paper_2403_13406_amd import workloads as W
+from test_gpu_parity import initial_u, small, solver_for
+
+pytestmark = pytest.mark.gpu
+ADJ_RTOL = 1e-11
+
+
+@pytest.mark.parametrize("name", ["burgers1d", "sw1d", "euler2d", "sw2d", "burgers2d", "advection2d"])
+@pytest.mark.parametrize("relax", ["fixed", "entropic"])
+def test_relax_adjoint_pass(name, relax):
+    w = small(name)
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    h = off_equilibrium(lat, sys, w.V, initial_u(w), shift=3)
+    gbar = np.random.default_rng(30).standard_normal(h.shape)
+    s = solver_for(w, relax)
+    out = to_gpu(gbar)
+    s.relax_adjoint(to_gpu(h), out)
+    assert s.sync() == 0
+    want = relax_adjoint(lat, sys, w.V, h, gbar, relax, 2.0)
+    err = componentwise_error(to_host(out), want)
+    assert max(err) <= ADJ_RTOL, err
+
+
+@pytest.mark.parametrize("name,nsteps,ck", [("euler2d", 2, 1), ("sw1d", 3, 2), ("burgers1d", 4, 3), ("sw2d", 2, 5)])
+def test_adjoint_through_steps(name, nsteps, ck):
+    """eslb_adjoint (checkpointing + recomputation) equals the oracle's taped reverse sweep."""
+    w = small(name)
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    u = initial_u(w)
+    s = solver_for(w, "entropic")
+    f0 = s.init_equilibrium(to_gpu(u))
+    fbarT = np.random.default_rng(31).standard_normal(f0.shape)
+    fb = to_gpu(fbarT)
+    s.adjoint(f0, nsteps, ck, fb)
+    assert s.sync() == 0
+    assert s.offsets == [0] * s.q
+    want = adjoint_run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u), nsteps, fbarT)
+    got = to_host(fb)
+    err = componentwise_error(got, want)
+    assert max(err) <= 1e-9, err
+    for m in range(want.shape[1]):
+        l2 = np.linalg.norm(got[:, m] - want[:, m]) / np.linalg.norm(want[:, m])
+        assert l2 <= ADJ_RTOL, (m, l2)
+
+
+def test_checkpoint_interval_does_not_change_the_result():
+    """Recomputation is deterministic, so any checkpoint interval gives the same bits."""
+    w = small("euler2d")
+    u = initial_u(w)
+    s = solver_for(w, "entropic")
+    f0 = s.init_equilibrium(to_gpu(u))
+    fbarT = to_gpu(np.random.default_rng(32).standard_normal(f0.shape))
+    outs = []
+    for ck in (1, 2, 5, 50):
+        fb = fbarT.clone()
+        s.adjoint(f0, 5, ck, fb)
+        s.sync()
+        outs.append(to_host(fb))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_autograd_misfit_gradient_against_oracle_and_finite_differences():
+    """dL/dU0 for L = 1/2 |U(T) - U_target|^2 through the torch.autograd.Function."""
+    import torch
+
+    from paper_2403_13406_amd.autograd import time_loop
+    w = W.euler2d(40, ny=36, nsteps=3, amp=0.01)
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    u0 = w.initial_state()
+    ut = W.euler2d(40, ny=36, nsteps=3, amp=0.01, seed=1).initial_state()
+    s = solver_for(w, "entropic")
+    x = to_gpu(u0).requires_grad_(True)
+    uT = time_loop(x, s, w.nsteps, ckpt_every=2)
+    L = 0.5 * torch.sum((uT - to_gpu(ut)) ** 2)
+    L.backward()
+    g = to_host(x.grad)
+    Lo, go = misfit_gradient(Relaxer(lat, sys, w.V, "entropic"), u0, ut, w.nsteps)
+    assert abs(float(L) - Lo) <= 1e-12 * Lo
+    assert max(componentwise_error(g[None], go[None])) <= 1e-9
+    for m in range(go.shape[0]):
+        assert np.linalg.norm(g[m] - go[m]) / np.linalg.norm(go[m]) <= ADJ_RTOL
+    rng = np.random.default_rng(2)
+
+    def loss(uu):
+        with torch.no_grad():
+            return float(0.5 * torch.sum((time_loop(to_gpu(uu), s, w.nsteps) - to_gpu(ut)) ** 2))
+
+    for _ in range(4):
+        dl = rng.standard_normal(u0.shape)
+        e = 1e-6
+        fd = (loss(u0 + e * dl) - loss(u0 - e * dl)) / (2 * e)
+        assert abs(fd - float(np.sum(g * dl))) <= 1e-7 * abs(fd)

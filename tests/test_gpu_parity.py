@@ -42,8 +42,9 @@ def small(name):
 
 def initial_u(w):
     if w.name.startswith("burgers2d") or w.name.startswith("advection2d"):
+        # smooth enough that Burgers stays shock-free over 10 steps (t = 2.4 at 50 x 31, V = 2)
         rng = np.random.default_rng(w.seed)
-        return (0.3 + W.spectral_field_2d(w.nx, w.ny, rng, 4, 0.2))[None]
+        return (0.3 + W.spectral_field_2d(w.nx, w.ny, rng, 1, 0.03))[None]
     return w.initial_state()
 
 
@@ -146,7 +147,6 @@ def test_full_size_euler_step_sampled():
     g = s.gather(f)
     rng = np.random.default_rng(12)
     R = 36
-    f0 = None
     for _ in range(4):
         cy, cx = (int(v) for v in rng.integers(0, 4096, size=2))
         ys = (np.arange(cy - R, cy + R + 1)) % 4096
@@ -156,8 +156,8 @@ def test_full_size_euler_step_sampled():
         want = fw[:, :, R, R]
         got = to_host(g[:, :, cy, cx])
         for m in range(4):
-            scale = np.max(np.abs(want[:, m]))
-            assert np.max(np.abs(got[:, m] - want[:, m])) <= PARITY_RTOL * max(scale, 1e-300) * 4
+            scale = np.max(np.abs(fw[:, m]))      # max |f_{k,m}| over the window
+            assert np.max(np.abs(got[:, m] - want[:, m])) <= PARITY_RTOL * scale
 
 
 # ------------------------------------------------------------------ diagnostics and edge cases
