@@ -1,22 +1,27 @@
 """Benchmark of the fourth-order entropy-stable LB time loop on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler2d|sw1d|burgers1d]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler2d|sw1d|burgers1d|batch|adjoint]
 
 A "step" is one composed fourth-order step Phi(dt) (eq. splittingToUse): 18
 passes "shift, entropic relax" over the whole grid.  The default workload is the
 2D Euler D2Q4^4 grid of 4096^2 cells (FP64, entropy-limited omega); inputs are
 seeded synthetic smooth fields resident in HBM before timing starts.
 
-Prints one JSON line:
-  value      = cells * K / timed seconds / 1e6 (MLUPS, whole job, one GPU)
-  roofline   = the stage kernel: algorithmic bytes per launch (2 q M 8 B per cell)
-               / its average launch duration (HIP events on the solver's stream over
-               the timed region, which holds stage kernels only) vs 8 TB/s HBM
-  cpu_baseline = the CPU oracle, single-threaded, on a bounded sample of the same
-               workload (a smaller grid of the same generator), in MLUPS.
+One JSON line:
+  value        cells * K / timed seconds / 1e6 (MLUPS, whole job, one GPU)
+  roofline     the stage kernel: algorithmic bytes per launch (2 q M 8 B per node)
+               / its average launch time (HIP events on the solver's stream around
+               the timed steps, which hold stage kernels only) vs 8 TB/s;
+               traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated
+               on a plain copy), from profiles/ when the kernel sources still match
+  cpu_baseline the CPU oracle, single-threaded, on a bounded sample of the workload
+  batch        (default run) a reduced sample of the batched ensemble: one
+               persistent-kernel batch run vs the plain per-instance loop, same GPU
+  adjoint      (default run) forward vs forward+adjoint with checkpointing on the
+               1024^2 Euler grid, same GPU
+--workload batch / adjoint run those two comparisons at their full sizes instead.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -27,17 +32,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM peak per 4th-order step; batched & adjoint vs plain same GPU"
 HBM_PEAK_GBS = 8000.0
-FP64_VECTOR_PEAK_TFLOPS = 78.6
-
-
-def source_hash():
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2403_13406_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
 
 
 def make_workload(name, size):
@@ -51,21 +45,21 @@ def make_workload(name, size):
     raise SystemExit("unknown workload %s" % name)
 
 
-def traffic_for(workload_tag):
-    """HBM bytes per stage launch from committed rocprofv3 --pmc summaries, if still current."""
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % workload_tag)
+def traffic_for(tag):
+    """HBM bytes per stage launch from the committed counter record, if still current."""
+    from paper_2403_13406_amd.profiling import source_hash
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % tag)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return round(rec["bytes_per_launch"], 0)
 
 
 def cpu_baseline(w, budget_s=15.0):
-    """Time the oracle (as it stands) on a bounded sample: the same generator on a small grid."""
-    import numpy as np
+    """The oracle (as it stands) timed on a bounded sample: the same generator on a small grid."""
     from threadpoolctl import threadpool_limits
 
     from oracle.lattice import Lattice
@@ -76,9 +70,12 @@ def cpu_baseline(w, budget_s=15.0):
     if w.system == "euler":
         sample = W.euler2d(64, nsteps=1)
         lat, sys_ = Lattice("D2Q4"), Euler(w.param[0], 2)
-    elif w.system == "shallow_water":
+    elif w.system == "shallow_water" and w.lattice == "D1Q2":
         sample = W.sw1d(4096, nsteps=1)
         lat, sys_ = Lattice("D1Q2"), ShallowWater(w.param[0], 1)
+    elif w.system == "shallow_water":
+        sample = W.Workload("sw2d_sample", "D2Q4", "shallow_water", 64, 64, 8.0, (9.81,), 1, 1000)
+        lat, sys_ = Lattice("D2Q4"), ShallowWater(w.param[0], 2)
     else:
         sample = W.burgers1d(w.nx)
         lat, sys_ = Lattice("D1Q2"), Burgers((1.0,))
@@ -92,33 +89,27 @@ def cpu_baseline(w, budget_s=15.0):
             f = composed_step(r, f)
             steps += 1
             el = time.perf_counter() - t0
-            if el > budget_s or steps >= sample.nsteps * 50:
+            if el > budget_s or steps >= 200:
                 break
     cells = sample.nx * sample.ny
-    return {"value": cells * steps / el / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "%s %dx%d, %d composed entropic steps, %.1f s, numpy single thread"
+    return {"value": round(cells * steps / el / 1e6, 5), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "%s %dx%d, %d composed entropic steps in %.1f s, numpy single thread"
                       % (sample.name, sample.nx, sample.ny, steps, el)}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="euler2d")
-    ap.add_argument("--size", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
-              file=sys.stderr)
-        sys.exit(2)
+def timed_steps(s, f, steps, torch):
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(s.stream)
+    s.step(f, steps)
+    ev1.record(s.stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
 
-    import numpy as np
-    import torch
 
+def bench_single(args, torch):
     from paper_2403_13406_amd import Solver
-
     w = make_workload(args.workload, args.size)
     u0 = torch.from_numpy(w.initial_state()).cuda()
     s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax=w.relax, param=w.param)
@@ -126,27 +117,23 @@ def main():
     del u0
     s.step(f, args.warmup)
     s.sync()
-    stream = s.stream
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    s.step(f, args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    ms = timed_steps(s, f, args.steps, torch)
     status = s.sync()
-    cells = w.cells
-    value = cells * args.steps / (ms / 1e3) / 1e6
+    if args.calibrate_copy_mib:
+        # a plain device-to-device copy of known size, for the counter calibration
+        n = args.calibrate_copy_mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
     passes = 18
     avg_launch_s = ms / 1e3 / (args.steps * passes)
-    bytes_per_launch = 2 * s.q * s.M * 8 * cells
+    bytes_per_launch = 2 * s.q * s.M * 8 * w.cells
     achieved = bytes_per_launch / avg_launch_s / 1e9
     tag = "%s_%dx%d" % (w.name, w.nx, w.ny)
-    traffic = traffic_for(tag)
     rec = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": round(w.cells * args.steps / (ms / 1e3) / 1e6, 3),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -160,12 +147,142 @@ def main():
         "config": {"workload": tag, "lattice": w.lattice, "system": w.system, "nx": w.nx, "ny": w.ny,
                    "V": w.V, "relax": w.relax, "steps_in_workload": w.nsteps, "passes_per_step": passes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(tag)},
         "stage_kernel_avg_us": round(avg_launch_s * 1e6, 2),
         "status": status,
-        "source_hash": source_hash(),
     }
+    del f
+    return rec, w
+
+
+def batch_compare(torch, count, steps_scale, tune=True, seed_base=0):
+    """Batched ensemble (one persistent kernel) vs the plain per-instance loop, same GPU."""
+    import numpy as np
+
+    from paper_2403_13406_amd import Batch, Solver
+    from paper_2403_13406_amd import workloads as W
+    ws = [W.sw2d_instance(i) for i in range(seed_base, seed_base + count)]
+    steps = [max(1, int(round(w.nsteps * steps_scale))) for w in ws]
+    b = Batch([dict(lattice=w.lattice, system=w.system, nx=w.nx, ny=w.ny, V=w.V, relax="entropic",
+                    param=w.param) for w in ws])
+    solvers, f_batch, f_plain = [], [], []
+    for w in ws:
+        s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
+        f = s.init_equilibrium(torch.from_numpy(w.initial_state()).cuda())
+        solvers.append(s)
+        f_batch.append(f)
+        f_plain.append(f.clone())
+    cfg = None
+    if tune:
+        cfg, _ = b.autotune(f_batch, trial_steps=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(f_batch, steps)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for s, f, n in zip(solvers, f_plain, steps):
+        s.step(f, n)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = all(bool(torch.equal(a, c)) for a, c in zip(f_batch, f_plain))
+    cell_steps = sum(w.cells * n for w, n in zip(ws, steps))
+    return {"instances": count, "cells": sum(w.cells for w in ws), "cell_steps": cell_steps,
+            "steps_scale": steps_scale, "batch_mlups": round(cell_steps / t_batch / 1e6, 2),
+            "per_instance_mlups": round(cell_steps / t_plain / 1e6, 2),
+            "speedup_vs_per_instance": round(t_plain / t_batch, 3), "bitwise_equal_to_per_instance": same,
+            "autotuned_config": cfg, "batch_s": round(t_batch, 3), "per_instance_s": round(t_plain, 3)}
+
+
+def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
+    """Forward vs forward + hand-written adjoint (checkpointing) for L = 1/2 |U(T) - U_target|^2."""
+    import numpy as np
+
+    from paper_2403_13406_amd import Solver
+    from paper_2403_13406_amd import workloads as W
+    from paper_2403_13406_amd.autograd import time_loop
+    w = W.euler2d_adjoint(n, nsteps=nsteps)
+    s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
+    u0 = torch.from_numpy(W.euler2d(n, seed=0, amp=0.005).initial_state()).cuda()
+    ut = torch.from_numpy(W.euler2d(n, seed=1, amp=0.005).initial_state()).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        uT = time_loop(u0, s, nsteps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    x = u0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = 0.5 * torch.sum((time_loop(x, s, nsteps, ckpt) - ut) ** 2)
+    L.backward()
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    rec = {"grid": "%dx%d" % (n, n), "steps": nsteps, "ckpt_every": ckpt,
+           "forward_s": round(t_fwd, 3), "forward_plus_adjoint_s": round(t_adj, 3),
+           "ratio_to_forward": round(t_adj / t_fwd, 3),
+           "workspace_GiB": round(s.adjoint_workspace_bytes(nsteps, ckpt) / 2 ** 30, 3)}
+    if fd_dirs:
+        rng = np.random.default_rng(w.extra["fd_seed"])
+        g = x.grad
+        worst = 0.0
+        for _ in range(fd_dirs):
+            dl = torch.from_numpy(rng.standard_normal(tuple(u0.shape))).cuda()
+            e = 1e-6
+            with torch.no_grad():
+                Lp = float(0.5 * torch.sum((time_loop(u0 + e * dl, s, nsteps) - ut) ** 2))
+                Lm = float(0.5 * torch.sum((time_loop(u0 - e * dl, s, nsteps) - ut) ** 2))
+            fd = (Lp - Lm) / (2 * e)
+            ad = float(torch.sum(g * dl))
+            worst = max(worst, abs(fd - ad) / abs(fd))
+        rec["fd_directions"] = fd_dirs
+        rec["fd_max_rel_diff"] = worst
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="euler2d")
+    ap.add_argument("--size", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the reduced batch/adjoint comparisons")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0)
+    ap.add_argument("--batch-steps-scale", type=float, default=1.0)
+    ap.add_argument("--fd-dirs", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.workload == "batch":
+        r = batch_compare(torch, 512, args.batch_steps_scale)
+        rec = {"metric": METRIC, "value": r["batch_mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": None,
+               "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f64", "data": "synthetic",
+               "config": {"workload": "sw2d_batch_512", "lattice": "D2Q4", "system": "shallow_water"},
+               "batch": r}
+        print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "adjoint":
+        r = adjoint_compare(torch, 1024, 2000, 50, args.fd_dirs)
+        rec = {"metric": METRIC, "value": round(1024 * 1024 * 2000 / r["forward_plus_adjoint_s"] / 1e6, 3),
+               "unit": "MLUPS (forward+adjoint)", "n_gpus": 1, "steps": 2000, "warmup": 0, "ms_per_step": None,
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+               "data": "synthetic", "config": {"workload": "euler2d_adjoint_1024x1024"}, "adjoint": r}
+        print(json.dumps(rec), flush=True)
+        return
+
+    rec, w = bench_single(args, torch)
+    if not args.no_extras and args.workload == "euler2d":
+        torch.cuda.empty_cache()
+        rec["batch"] = batch_compare(torch, 48, 0.05)
+        torch.cuda.empty_cache()
+        rec["adjoint"] = adjoint_compare(torch, 1024, 100, 50)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)
