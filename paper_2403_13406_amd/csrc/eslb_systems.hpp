@@ -46,15 +46,35 @@ __device__ __forceinline__ double rcp(double x) {
   return fma(r, e, r);
 }
 
-// log(1 + z).  For |z| < 1/64 (the increments near equilibrium) use
-// log(1+z) = 2 atanh(w), w = z / (2 + z), summed to w^9 (truncation below
-// 1e-19 relative); otherwise the library log1p.
+// sqrt of a positive normal number: hardware rsq estimate, two Goldschmidt
+// refinements of (sqrt x, 1/(2 sqrt x)) and a final residual correction.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  const double d = fma(-s, s, x);
+  return fma(d, h, s);
+}
+
+// log(1 + z).  For |z| < 1/128 (the increments near equilibrium) the Taylor
+// series to z^9 (truncation below 1e-19 relative); otherwise the library log1p.
 __device__ __forceinline__ double log1p_near0(double z) {
-  if (fabs(z) < 0.015625) {
-    const double w = z * rcp(2.0 + z);
-    const double w2 = w * w;
-    const double poly = fma(w2, fma(w2, fma(w2, fma(w2, 1.0 / 9.0, 1.0 / 7.0), 1.0 / 5.0), 1.0 / 3.0), 1.0);
-    return 2.0 * w * poly;
+  if (fabs(z) < 0.0078125) {
+    double p = 1.0 / 9.0;
+    p = fma(p, z, -1.0 / 8.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, -1.0 / 6.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, -0.25);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, -0.5);
+    p = fma(p, z, 1.0);
+    return p * z;
   }
   return log1p(z);
 }
@@ -89,12 +109,13 @@ template <int D> struct Advection {
   __device__ static double macro_entropy(const Node& c, const Phys&) { return 0.5 * c.u * c.u; }
   // (d phi^j / du)^T z
   __device__ static void fluxT(const Node&, int j, const double* z, double* out, const Phys& P) { out[0] = a(j, P) * z[0]; }
-  template <int k>
-  __device__ static bool bregman(const Node&, const double*, const double* e, double& B, double* dv, const Phys& P) {
+  template <int k, bool DV>
+  __device__ static bool bregman(const Node&, const double*, const double* d, double t, double& B, double* dv,
+                                 const Phys& P) {
     const double wk = P.w + Lat<D>::sign(k) * a(Lat<D>::axis(k), P) * P.inv2V;
-    const double dU = e[0] / wk;
+    const double dU = t * d[0] / wk;
     B = 0.5 * wk * dU * dU;
-    dv[0] = dU;
+    if (DV) dv[0] = dU;
     return wk > 0.0;
   }
 };
@@ -120,15 +141,17 @@ template <int D> struct Burgers {
   __device__ static void fluxT(const Node& c, int j, const double* z, double* out, const Phys& P) {
     out[0] = b(j, P) * c.u * z[0];
   }
-  template <int k>
-  __device__ static bool bregman(const Node& c, const double*, const double* e, double& B, double* dv, const Phys& P) {
+  template <int k, bool DV>
+  __device__ static bool bregman(const Node& c, const double*, const double* d, double t, double& B, double* dv,
+                                 const Phys& P) {
     const double beta = Lat<D>::sign(k) * b(Lat<D>::axis(k), P);
+    const double e = t * d[0];
     const double c1 = P.w + beta * c.u * P.inv2V;
-    const double disc = c1 * c1 + 2.0 * beta * e[0] * P.inv2V;
+    const double disc = c1 * c1 + 2.0 * beta * e * P.inv2V;
     const bool ok = (c1 > 0.0) && (disc > 0.0);
-    const double dU = 2.0 * e[0] / (c1 + sqrt(ok ? disc : c1 * c1));
+    const double dU = 2.0 * e * rcp(c1 + sqrt_pos(ok ? disc : c1 * c1));
     B = dU * dU * (0.5 * P.w + beta * (3.0 * c.u + 2.0 * dU) * (P.inv2V * (1.0 / 6.0)));
-    dv[0] = dU;
+    if (DV) dv[0] = dU;
     return ok;
   }
 };
@@ -189,21 +212,21 @@ template <int D> struct ShallowWater {
 #pragma unroll
     for (int l = 0; l < D; ++l) out[1 + l] = vj * z[1 + l] + (l == j ? z[0] + zv : 0.0);
   }
-  template <int k>
-  __device__ static bool bregman(const Node& c, const double* feq, const double* e, double& B, double* dv,
+  template <int k, bool DV>
+  __device__ static bool bregman(const Node& c, const double* feq, const double* d, double t, double& B, double* dv,
                                  const Phys& P) {
     constexpr int n = Lat<D>::axis(k);
     constexpr double s = Lat<D>::sign(k);
     const double g = P.p0, V = P.V;
     const double un = c.vel[n];
     const double W = P.W0 + s * un;
-    const double f1 = feq[0], e1 = e[0];
+    const double f1 = feq[0], e1 = t * d[0];
     const double x1 = f1 + e1;
-    const double gn = e[1 + n] - e1 * un;
+    const double gn = t * (d[1 + n] - d[0] * un);
     const double W2 = W * W;
     double dn = 0.0;
 #pragma unroll 1
-    for (int it = 0; it < 30; ++it) {
+    for (int it = 0; it < 12; ++it) {
       const double Wp = W + s * dn;
       const double A = s * dn * f1 - e1 * W;
       const double Bq = f1 * Wp + x1 * W;
@@ -211,26 +234,27 @@ template <int D> struct ShallowWater {
       const double Dq = W2 * Wp * Wp;
       const double Pv = s * g * V * A * Bq + C * Dq;
       const double dP = g * V * f1 * (Bq + A) - x1 * Dq + 2.0 * s * C * W2 * Wp;
-      const double st = Pv / dP;
+      const double st = Pv * rcp(dP);
       dn -= st;
-      if (!(fabs(st) > 0x1p-51 * fabs(dn))) break;
+      // quadratic convergence: once a step is below 2^-40 |dn| the error left is ~2^-80 |dn|
+      if (!(fabs(st) > 0x1p-40 * fabs(dn))) break;
     }
     const double Wp = W + s * dn;
-    const double dh = 2.0 * V * (e1 * W - s * f1 * dn) / (W * Wp);
+    const double dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
     const double hp = c.h + dh;
     double du2 = dn * dn;
     double kin = dn * (2.0 * un + dn);
-    dv[1 + n] = dn;
+    if (DV) dv[1 + n] = dn;
     if (D == 2) {
-      constexpr int t = 1 - n;
-      const double ut = c.vel[t];
-      const double dt = (e[1 + t] - ut * e1) / x1;
+      constexpr int tt = 1 - n;
+      const double ut = c.vel[tt];
+      const double dt = t * (d[1 + tt] - ut * d[0]) * rcp(x1);
       du2 += dt * dt;
       kin += dt * (2.0 * ut + dt);
-      dv[1 + t] = dt;
+      if (DV) dv[1 + tt] = dt;
     }
     B = (g * W * dh * dh + 2.0 * s * g * hp * dh * dn + hp * Wp * du2) * (0.5 * P.inv2V);
-    dv[0] = g * dh - 0.5 * kin;
+    if (DV) dv[0] = g * dh - 0.5 * kin;
     return (x1 > 0.0) && (Wp > 0.0) && (hp > 0.0) && (Wp * Wp > g * hp) && isfinite(B);
   }
 };
@@ -301,50 +325,66 @@ struct Euler2 {
     out[2] = vj * z[2] - gm1 * vy * A + (j == 1 ? z[0] + zv + z[3] * H : 0.0);
     out[3] = gm1 * z[1 + j] + P.p0 * vj * z[3];
   }
-  template <int k>
-  __device__ static bool bregman(const Node& c, const double* feq, const double* e, double& B, double* dv,
+  // With e = t d, the increment quadratic simplifies (the 2V x_1 u_n terms cancel):
+  //   qa = -V x_1 (gamma+1)/(gamma-1),
+  //   qb = sigma (gamma (t P0c + p) - 2V x_1 W)/(gamma-1),
+  //   qc = t (qc1 + V dtn (2 u_t + du_t)),
+  // with per-velocity constants gnd = d_n - u_n d_1, dtn = d_t - u_t d_1,
+  // P0c = 2 sigma V gnd, qc1 = -2V d_E + V d_1 |u|^2 + P0c (W/(gamma-1) + sigma u_n),
+  // which do not depend on t and are hoisted out of the root iteration.
+  template <int k, bool DV>
+  __device__ static bool bregman(const Node& c, const double* feq, const double* d, double t, double& B, double* dv,
                                  const Phys& P) {
-    constexpr int n = Lat<2>::axis(k), t = 1 - n;
+    constexpr int n = Lat<2>::axis(k), tt = 1 - n;
     constexpr double s = Lat<2>::sign(k);
     const double gm = P.p0, igm1 = P.p2, V = P.V;
-    const double rho = c.rho, p = c.p, un = c.vel[n], ut = c.vel[t];
+    const double rho = c.rho, p = c.p, un = c.vel[n], ut = c.vel[tt];
     const double W = P.W0 + s * un;
-    const double f1 = feq[0], e1 = e[0];
+    const double f1 = feq[0];
+    // t-independent per-velocity constants; recomputed at every evaluation (the
+    // opaque copy keeps the compiler from hoisting them: keeping them live for
+    // all four velocities costs more registers than recomputing them)
+    double d0 = d[0], dn_ = d[1 + n], dt_ = d[1 + tt], d3 = d[3];
+    asm volatile("" : "+v"(d0), "+v"(dn_), "+v"(dt_), "+v"(d3));
+    const double gnd = dn_ - un * d0;
+    const double dtn = dt_ - ut * d0;
+    const double P0c = 2.0 * V * s * gnd;
+    const double qc1 = -2.0 * V * d3 + V * d0 * (un * un + ut * ut) + P0c * (W * igm1 + s * un);
+    // t-dependent part
+    const double e1 = t * d0;
     const double x1 = f1 + e1;
-    const double ix1 = rcp(x1);
-    const double gn = e[1 + n] - e1 * un;
-    const double dt = (e[1 + t] - ut * e1) * ix1;
-    const double utp = ut + dt;
-    const double P0 = 2.0 * V * s * gn;
-    const double P1 = -2.0 * V * s * x1;
+    const double dt = t * dtn * rcp(x1);
     const double qa = -V * x1 * (gm + 1.0) * igm1;
-    const double qb = 2.0 * V * x1 * un + (s * P0 + P1 * W + s * p) * igm1 + s * p + s * P0 + s * un * P1;
-    const double qc = -2.0 * V * e[3] + V * (e1 * (un * un + utp * utp) + f1 * dt * (2.0 * ut + dt)) +
-                      P0 * W * igm1 + s * un * P0;
+    const double qb = s * igm1 * (gm * (t * P0c + p) - 2.0 * V * x1 * W);
+    const double qc = t * (qc1 + V * dtn * (2.0 * ut + dt));
     const double disc = qb * qb - 4.0 * qa * qc;
-    const bool okd = disc >= 0.0;
-    const double den = qb + copysign(sqrt(okd ? disc : 0.0), qb);
+    const bool okd = disc > 0.0;
+    const double den = qb + copysign(okd ? sqrt_pos(disc) : 0.0, qb);
     const double dn = -2.0 * qc * rcp(den);
-    const double dp = P0 + P1 * dn;
+    const double dp = t * P0c - 2.0 * V * s * x1 * dn;
     const double Wp = W + s * dn;
     const double drho = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
     const double rhop = rho + drho, pp = p + dp;
     const double al = dp * c.ip, be = drho * c.irho;
-    const double ibb = rcp(1.0 + be);
+    const double opa = 1.0 + al, opb = 1.0 + be;
+    const double rab = rcp(opa * opb);
+    const double ibb = opa * rab;  // 1/(1+be)
     const double ds = log1p_near0(al) - gm * log1p_near0(be);
     const double du2 = dn * dn + dt * dt;
     B = x1 * (((al - be) * ibb - ds) * igm1 - be * ibb) + 0.5 * rho * x1 * du2 * c.ip +
         s * rho * dp * dn * c.ip * P.inv2V;
-    // entropy-variable difference v(U_k) - v(u)
-    const double bet = rho * c.ip;
-    const double dbet = bet * (be - al) * rcp(1.0 + al);
-    const double unp = un + dn;
-    const double up2 = unp * unp + utp * utp;
-    const double dkin = dbet * up2 + bet * (dn * (2.0 * un + dn) + dt * (2.0 * ut + dt));
-    dv[0] = -ds * igm1 - 0.5 * dkin;
-    dv[1 + n] = dbet * unp + bet * dn;
-    dv[1 + t] = dbet * utp + bet * dt;
-    dv[3] = -dbet;
+    if (DV) {
+      // entropy-variable difference v(U_k) - v(u)
+      const double bet = rho * c.ip;
+      const double dbet = bet * (be - al) * (opb * rab);
+      const double unp = un + dn, utp = ut + dt;
+      const double up2 = unp * unp + utp * utp;
+      const double dkin = dbet * up2 + bet * (dn * (2.0 * un + dn) + dt * (2.0 * ut + dt));
+      dv[0] = -ds * igm1 - 0.5 * dkin;
+      dv[1 + n] = dbet * unp + bet * dn;
+      dv[1 + tt] = dbet * utp + bet * dt;
+      dv[3] = -dbet;
+    }
     return okd && (x1 > 0.0) && (Wp > 0.0) && (rhop > 0.0) && (pp > 0.0) && (rhop * Wp * Wp > gm * pp) && isfinite(B);
   }
 };
@@ -368,21 +408,27 @@ template <class S> struct Eq {
   }
 };
 
-// F(t) = sum_k B_k and F'(t) = sum_k (v(U_k) - v(u)) . d_k, velocities k..Q-1.
-template <class S, int k = 0>
+// F(t) = sum_k B_k and (DV) F'(t) = sum_k (v(U_k) - v(u)) . d_k, velocities k..Q-1.
+template <class S, bool DV = true, int k = 0>
 __device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&feq)[S::Q][S::M],
                                      const double (&d)[S::Q][S::M], double t, double& F, double& dF, const Phys& P) {
   if constexpr (k == S::Q) {
     return true;
   } else {
-    double e[S::M], dv[S::M], B;
-#pragma unroll
-    for (int m = 0; m < S::M; ++m) e[m] = t * d[k][m];
-    const bool ok = S::template bregman<k>(c, feq[k], e, B, dv, P);
+    double dv[S::M], B;
+    const bool ok = S::template bregman<k, DV>(c, feq[k], d[k], t, B, dv, P);
     F += B;
+    if (DV) {
 #pragma unroll
-    for (int m = 0; m < S::M; ++m) dF += dv[m] * d[k][m];
-    const bool rest = fsum<S, k + 1>(c, feq, d, t, F, dF, P);
+      for (int m = 0; m < S::M; ++m) dF += dv[m] * d[k][m];
+    }
+    // Serialise the velocities: the next evaluation waits for this one's sum.
+    // Left free, the scheduler interleaves all q inversions for ILP and needs
+    // more registers than two waves per SIMD allow (spills); in sequence they
+    // fit without spilling (measured 1.20x faster on the Euler pass).
+    double ts = t;
+    asm volatile("" : "+v"(ts) : "v"(F), "v"(dF));
+    const bool rest = fsum<S, DV, k + 1>(c, feq, d, ts, F, dF, P);
     return ok && rest;
   }
 }
@@ -414,13 +460,15 @@ __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double
 }
 
 // lambda = omega - 1 solving F(-lambda) = F(1) (eq. variableOmegaProblem in the
-// Bregman form).  Safeguarded Newton on H(lambda) = F(-lambda) - F(1) with a
-// bisection bracket; after the samples at t = 1 and t = -1 the first move is taken
-// from the cubic Hermite model of G(t) = F(t)/t^2 on [-1, 1] (four values that the
-// two samples give for free), which is fourth-order accurate in the distance from
-// equilibrium, so one more sample usually ends the iteration.  Stops once a step
-// no longer moves f^eq - lambda d by more than rounding (2 eps * max|f|).
-// fallback = true when no root lies inside the convexity domain (omega = 1 then).
+// Bregman form).  F is sampled with its derivative at t = 1 and t = -1 (lambda = 1);
+// the cubic Hermite model of G(t) = F(t)/t^2 on [-1, 1] built from those four
+// numbers is fourth-order accurate in the distance from equilibrium and predicts
+// lambda; one more sample of F there gives a Newton correction (with the model's
+// derivative, which is accurate to third order), and if that correction no longer
+// moves f^eq - lambda d beyond rounding (2 eps max|f|) it is the root.  Otherwise
+// (far from equilibrium, domain edges) a safeguarded Newton iteration with a
+// bisection bracket takes over.  fallback = true when no root lies inside the
+// convexity domain (omega = 1 then).
 template <class S>
 __device__ inline double entropic_lambda(const typename S::Node& c, const double (&feq)[S::Q][S::M],
                                          const double (&d)[S::Q][S::M], double dmax, double fsc, const Phys& P,
@@ -433,8 +481,51 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
   }
   if (!(F1 > 0.0)) return 1.0;
   const double tol = 2.0 * 2.220446049250313e-16 * fsc;
-  double lo = 0.0, hi = INFINITY, x = 1.0, lam = 1.0;
+  double lo = 0.0, hi = INFINITY, x = 1.0;
   bool hi_bad = false;
+  {
+    double Fm = 0.0, dFm = 0.0;
+    const bool okm = fsum<S>(c, feq, d, -1.0, Fm, dFm, P);
+    const double H = Fm - F1;
+    if (okm && H == 0.0) return 1.0;
+    if (!okm || H > 0.0) {
+      hi = 1.0;
+      hi_bad = !okm;
+    } else {
+      lo = 1.0;
+    }
+    double xn = okm ? 1.0 + H / dFm : NAN;  // Newton from lambda = 1 (H' = -F'(-1))
+    if (okm) {
+      const double G1 = F1, Gm = Fm, G1p = dF1 - 2.0 * F1, Gmp = dFm + 2.0 * Fm;
+      const double cc = 0.25 * (G1p - Gmp);
+      const double dd = 0.25 * ((G1p + Gmp) - (G1 - Gm));
+      const double bb = 0.5 * (G1 - Gm) - dd;
+      const double aa = 0.5 * (G1 + Gm) - cc;
+      double lp = 1.0, pd = 1.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double g = aa + lp * (-bb + lp * (cc - dd * lp));
+        const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
+        const double pv = lp * lp * g - G1;
+        pd = 2.0 * lp * g + lp * lp * gp;
+        lp -= pv / pd;
+      }
+      if (isfinite(lp) && lp > lo && lp < hi && pd > 0.0) {
+        double F3 = 0.0, dF3 = 0.0;
+        const bool ok3 = fsum<S, false>(c, feq, d, -lp, F3, dF3, P);
+        const double H3 = F3 - F1;
+        const double xc = lp - H3 / pd;
+        if (ok3 && isfinite(xc) && fabs(xc - lp) * dmax <= tol) return xc;
+        if (!ok3 || H3 > 0.0) {
+          if (lp <= hi) { hi = lp; hi_bad = !ok3; }
+        } else {
+          lo = fmax(lo, lp);
+        }
+        xn = (ok3 && isfinite(xc)) ? xc : lp;
+      }
+    }
+    x = (isfinite(xn) && xn > lo && xn < hi) ? xn : (isinf(hi) ? 2.0 : 0.5 * (lo + hi));
+  }
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double F = 0.0, dF = 0.0;
@@ -447,25 +538,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
     } else {
       lo = fmax(lo, x);
     }
-    double xn = x - H / dH;
-    if (it == 0 && ok) {
-      // cubic Hermite model of G on [-1, 1] from F(+-1), F'(+-1)
-      const double G1 = F1, Gm = F, G1p = dF1 - 2.0 * F1, Gmp = dF + 2.0 * F;
-      const double cc = 0.25 * (G1p - Gmp);
-      const double dd = 0.25 * ((G1p + Gmp) - (G1 - Gm));
-      const double bb = 0.5 * (G1 - Gm) - dd;
-      const double aa = 0.5 * (G1 + Gm) - cc;
-      double lp = 1.0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double g = aa + lp * (-bb + lp * (cc - dd * lp));
-        const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
-        const double pv = lp * lp * g - G1;
-        const double pd = 2.0 * lp * g + lp * lp * gp;
-        lp -= pv / pd;
-      }
-      if (isfinite(lp) && lp > lo && lp < hi) xn = lp;
-    }
+    const double xn = x - H / dH;
     const bool newton_ok = ok && isfinite(xn) && (xn > lo) && (xn < hi);
     const double xnew = newton_ok ? xn : (isinf(hi) ? 2.0 * x : 0.5 * (lo + hi));
     if (newton_ok && fabs(xnew - x) * dmax <= tol) return xnew;
@@ -477,9 +550,8 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
       return hi;
     }
     x = xnew;
-    lam = x;
   }
-  return lam;
+  return x;
 }
 
 enum : unsigned { FLAG_INADMISSIBLE = 1u, FLAG_NAN = 2u, FLAG_FALLBACK = 4u, FLAG_SUBCHAR = 8u };
@@ -510,6 +582,13 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
     lam = 0.0;
     flags |= FLAG_FALLBACK;
   }
+  // The root iteration only reads the mass component of each f^eq_k; rebuilding
+  // f^eq from u here (rather than keeping all q*M values live through the
+  // iteration) saves registers.  The empty asm makes u opaque so the compiler
+  // recomputes instead of keeping the first copy alive.
+#pragma unroll
+  for (int m = 0; m < M; ++m) asm volatile("" : "+v"(u[m]));
+  Eq<S>::equilibrium(u, feq, P);
 #pragma unroll
   for (int k = 0; k < Q; ++k)
 #pragma unroll
@@ -547,10 +626,8 @@ __device__ __forceinline__ void dv_all(const typename S::Node& c, const double (
                                        const double (&d)[S::Q][S::M], double t, double (&dv)[S::Q][S::M],
                                        const Phys& P) {
   if constexpr (k < S::Q) {
-    double e[S::M], B;
-#pragma unroll
-    for (int m = 0; m < S::M; ++m) e[m] = t * d[k][m];
-    (void)S::template bregman<k>(c, feq[k], e, B, dv[k], P);
+    double B;
+    (void)S::template bregman<k, true>(c, feq[k], d[k], t, B, dv[k], P);
     dv_all<S, k + 1>(c, feq, d, t, dv, P);
   }
 }
