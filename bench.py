@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM peak per 4th-order step; batched & adjoint vs plain same GPU"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (FMA counted as two)
 
 
 def make_workload(name, size):
@@ -45,17 +46,15 @@ def make_workload(name, size):
     raise SystemExit("unknown workload %s" % name)
 
 
-def traffic_for(tag):
-    """HBM bytes per stage launch from the committed counter record, if still current."""
+def counter_record(kind, tag):
+    """A committed rocprofv3 counter record (profiles/<kind>_<tag>.json) if the kernels still match it."""
     from paper_2403_13406_amd.profiling import source_hash
-    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % tag)
+    path = os.path.join(ROOT, "profiles", "%s_%s.json" % (kind, tag))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("source_hash") != source_hash():
-        return None
-    return round(rec["bytes_per_launch"], 0)
+    return rec if rec.get("source_hash") == source_hash() else None
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -131,6 +130,19 @@ def bench_single(args, torch):
     bytes_per_launch = 2 * s.q * s.M * 8 * w.cells
     achieved = bytes_per_launch / avg_launch_s / 1e9
     tag = "%s_%dx%d" % (w.name, w.nx, w.ny)
+    traffic = counter_record("traffic", tag)
+    valu = counter_record("valu", tag)
+    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": round(traffic["bytes_per_launch"]) if traffic else None}
+    if valu:
+        # the entropic pass is bound by FP64 arithmetic: FLOPs per node from the counters
+        tflops = valu["fp64_flop_per_node"] * w.cells / avg_launch_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "traffic": hbm["traffic"],
+                    "flop_per_node": valu["fp64_flop_per_node"]}
+    else:
+        roofline = hbm
     rec = {
         "metric": METRIC,
         "value": round(w.cells * args.steps / (ms / 1e3) / 1e6, 3),
@@ -146,8 +158,8 @@ def bench_single(args, torch):
         "data": "synthetic",
         "config": {"workload": tag, "lattice": w.lattice, "system": w.system, "nx": w.nx, "ny": w.ny,
                    "V": w.V, "relax": w.relax, "steps_in_workload": w.nsteps, "passes_per_step": passes},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(tag)},
+        "roofline": roofline,
+        "hbm": hbm,
         "stage_kernel_avg_us": round(avg_launch_s * 1e6, 2),
         "status": status,
     }
@@ -155,9 +167,12 @@ def bench_single(args, torch):
     return rec, w
 
 
+def progress(msg):
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 def batch_compare(torch, count, steps_scale, tune=True, seed_base=0):
     """Batched ensemble (one persistent kernel) vs the plain per-instance loop, same GPU."""
-    import numpy as np
 
     from paper_2403_13406_amd import Batch, Solver
     from paper_2403_13406_amd import workloads as W
@@ -166,23 +181,35 @@ def batch_compare(torch, count, steps_scale, tune=True, seed_base=0):
     b = Batch([dict(lattice=w.lattice, system=w.system, nx=w.nx, ny=w.ny, V=w.V, relax="entropic",
                     param=w.param) for w in ws])
     solvers, f_batch, f_plain = [], [], []
-    for w in ws:
+    for i, w in enumerate(ws):
         s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
         f = s.init_equilibrium(torch.from_numpy(w.initial_state()).cuda())
         solvers.append(s)
         f_batch.append(f)
         f_plain.append(f.clone())
+        if (i + 1) % 64 == 0:
+            progress("batch: %d/%d instances initialised" % (i + 1, count))
     cfg = None
     if tune:
         cfg, _ = b.autotune(f_batch, trial_steps=1)
+        progress("batch: autotuned config %s" % cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.run(f_batch, steps)
+    left = list(steps)
+    while max(left) > 0:     # chunks of at most 100 steps; the batch keeps every instance's offsets
+        chunk = [min(100, n) for n in left]
+        b.run(f_batch, chunk)
+        left = [n - c for n, c in zip(left, chunk)]
+        progress("batch: ensemble %d steps left at most (%.1f s)" % (max(left), time.perf_counter() - t0))
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    progress("batch: ensemble run %.2f s" % t_batch)
     t0 = time.perf_counter()
-    for s, f, n in zip(solvers, f_plain, steps):
+    for i, (s, f, n) in enumerate(zip(solvers, f_plain, steps)):
         s.step(f, n)
+        if (i + 1) % 16 == 0:
+            torch.cuda.synchronize()
+            progress("batch: per-instance %d/%d (%.1f s)" % (i + 1, count, time.perf_counter() - t0))
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     same = all(bool(torch.equal(a, c)) for a, c in zip(f_batch, f_plain))
@@ -211,6 +238,7 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
         uT = time_loop(u0, s, nsteps)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    progress("adjoint: forward %d steps %.2f s" % (nsteps, t_fwd))
     x = u0.clone().requires_grad_(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -218,6 +246,7 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
     L.backward()
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
+    progress("adjoint: forward + adjoint %.2f s" % t_adj)
     rec = {"grid": "%dx%d" % (n, n), "steps": nsteps, "ckpt_every": ckpt,
            "forward_s": round(t_fwd, 3), "forward_plus_adjoint_s": round(t_adj, 3),
            "ratio_to_forward": round(t_adj / t_fwd, 3),
@@ -235,6 +264,7 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
             fd = (Lp - Lm) / (2 * e)
             ad = float(torch.sum(g * dl))
             worst = max(worst, abs(fd - ad) / abs(fd))
+            progress("adjoint: FD direction rel diff %.3e" % (abs(fd - ad) / abs(fd)))
         rec["fd_directions"] = fd_dirs
         rec["fd_max_rel_diff"] = worst
     return rec
@@ -243,8 +273,8 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="euler2d")
     ap.add_argument("--size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")

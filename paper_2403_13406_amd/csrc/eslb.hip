@@ -247,6 +247,118 @@ __global__ __launch_bounds__(256) void k_init_adjoint(const double* __restrict__
   for (int m = 0; m < M; ++m) ubar[(long long)m * plane + i] = out[m];
 }
 
+// Whole run in one workgroup for domains whose state fits in LDS: the state is
+// loaded once in logical layout, every pass of every step runs on LDS with the
+// same offset addressing as k_stage (barriers between passes), and the state is
+// written back once with the final offsets.  For small grids where a pass is a
+// few microseconds of work and a launch per pass would dominate.
+struct RunPlan {
+  int npass;
+  int trailing;
+  int shift[32];
+  int op[32];           // 0: relax with the context's omega, 1: projection R_1
+  long long o_start[4]; // offsets of the velocities when the run starts
+};
+
+template <int D>
+__device__ __forceinline__ int lds_index(int k, int x, int y, int nx, int ny, long long o) {
+  const int axis = Lat<D>::axis(k);
+  const int sign = Lat<D>::sign(k);
+  if (axis == 0) {
+    long long xs = ((long long)x - sign * o) % nx;
+    if (xs < 0) xs += nx;
+    return y * nx + (int)xs;
+  }
+  long long ys = ((long long)y - sign * o) % ny;
+  if (ys < 0) ys += ny;
+  return (int)ys * nx + x;
+}
+
+// Block size: the heavy systems (12-16 populations per node) run 256 threads so
+// they keep their registers; the light ones use up to 1024.
+template <class S>
+constexpr int run_lds_threads() {
+  return S::Q * S::M >= 12 ? 256 : 1024;
+}
+
+template <class S, int D>
+__global__ __launch_bounds__(run_lds_threads<S>()) void k_run_lds(Grid g, Phys P, int mode, RunPlan plan,
+                                                                   long long nsteps, DevStats* st) {
+  constexpr int Q = S::Q, M = S::M;
+  extern __shared__ double lds[];
+  const int ncell = g.nx * g.ny;
+  // load: logical f_k(x) = storage at x - o_start c_k
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+    const int x = i % g.nx, y = i / g.nx;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const long long id = storage_index<D>(g, k, x, y);
+#pragma unroll
+      for (int m = 0; m < M; ++m) lds[(k * M + m) * ncell + i] = g.f[(long long)(k * M + m) * g.plane + id];
+    }
+  }
+  unsigned flags = 0;
+  long long o = 0;  // offset of the LDS copy relative to the loaded logical layout
+  for (long long step = 0; step < nsteps; ++step) {
+    for (int p = 0; p < plan.npass; ++p) {
+      o += plan.shift[p];
+      Phys Pp = P;
+      int md = mode;
+      if (plan.op[p]) {
+        Pp.omega = 1.0;
+        md = 0;
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+        const int x = i % g.nx, y = i / g.nx;
+        int id[Q];
+        double f[Q][M];
+#pragma unroll
+        for (int k = 0; k < Q; ++k) {
+          id[k] = lds_index<D>(k, x, y, g.nx, g.ny, o);
+#pragma unroll
+          for (int m = 0; m < M; ++m) f[k][m] = lds[(k * M + m) * ncell + id[k]];
+        }
+        relax_node<S>(f, md, Pp, flags);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) {
+            if (!isfinite(f[k][m])) flags |= FLAG_NAN;
+            lds[(k * M + m) * ncell + id[k]] = f[k][m];
+          }
+      }
+    }
+    o += plan.trailing;
+  }
+  __syncthreads();
+  // write back: storage position of logical x after the run is x - (o_start + o) c_k,
+  // and the LDS holds it at x - o c_k
+  Grid ge = g;
+  for (int k = 0; k < Q; ++k) {
+    const int axis = (D == 1) ? 0 : (k & 1);
+    const int sign = (k < Q / 2) ? 1 : -1;
+    const long long n = axis == 0 ? g.nx : g.ny;
+    long long sh = (-(long long)sign * (plan.o_start[k] + o)) % n;
+    if (sh < 0) sh += n;
+    ge.sh[k] = (int)sh;
+  }
+  for (int i = threadIdx.x; i < ncell; i += blockDim.x) {
+    const int x = i % g.nx, y = i / g.nx;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const long long id = storage_index<D>(ge, k, x, y);
+      const int li = lds_index<D>(k, x, y, g.nx, g.ny, o);
+#pragma unroll
+      for (int m = 0; m < M; ++m) g.f[(long long)(k * M + m) * g.plane + id] = lds[(k * M + m) * ncell + li];
+    }
+  }
+  if (flags) {
+    atomicOr(&st->flags, flags);
+    if (flags & FLAG_FALLBACK) atomicAdd(&st->n_fallback, 1ull);
+  }
+}
+
 // Diagnostics, pass 1: per-block partial sums in a fixed tree order.
 // Layout of a block's partials: mass[M], micro, macro (NV = M + 2 doubles).
 constexpr int kDiagThreads = 256;
@@ -565,6 +677,32 @@ size_t adjoint_states(const eslb_ctx* c, int64_t nsteps, int64_t ck) {
   return (size_t)nseg + (size_t)ck + c->passes.size() + 2;
 }
 
+// Whole run in LDS (see k_run_lds); all velocities share one offset history here.
+int run_small(eslb_ctx* c, double* f, int64_t nsteps) {
+  RunPlan plan;
+  plan.npass = (int)c->passes.size();
+  plan.trailing = c->trailing;
+  for (int p = 0; p < plan.npass; ++p) {
+    plan.shift[p] = c->passes[p].shift;
+    plan.op[p] = c->passes[p].op == PASS_PROJECT ? 1 : 0;
+  }
+  const Grid g = make_grid(c, f);
+  const long long ncell = (long long)c->pb.nx * c->pb.ny;
+  const size_t lds = (size_t)c->q * c->M * ncell * sizeof(double);
+  for (int k = 0; k < 4; ++k) plan.o_start[k] = c->off[k];
+  Phys P = c->phys;
+  const int mode = c->pb.relax;
+#define CALL(S, D)                                                                                          \
+  hipLaunchKernelGGL((k_run_lds<S, D>), dim3(1),                                                            \
+                     dim3((int)std::min<long long>(run_lds_threads<S>(), ((ncell + 63) / 64) * 64)), lds,   \
+                     c->stream, g, P, mode, plan, (long long)nsteps, c->st)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  const int rc = hip_check(c, hipGetLastError(), "whole-run kernel launch");
+  if (rc == ESLB_OK) add_offsets(c, (long long)nsteps * net_shift(c));
+  return rc;
+}
+
 }  // namespace eslb
 
 // ------------------------------------------------------------------ C ABI
@@ -609,6 +747,8 @@ int eslb_create(const eslb_problem* p, void* stream, eslb_ctx** out) {
   for (int k = 0; k < 4; ++k) c->off[k] = 0;
   c->phys = make_phys(*p, q);
   build_schedule(c);
+  // whole run in one workgroup's LDS when the state is at most 64 KiB
+  c->small_run = ((size_t)q * M * (size_t)p->nx * p->ny * sizeof(double) <= 65536) && c->passes.size() <= 32;
   c->diag_blocks = 1024;
   const int nv = M + 2;
   hipError_t e = hipMalloc(&c->st, sizeof(DevStats));
@@ -685,6 +825,7 @@ int eslb_init_equilibrium(eslb_ctx* c, const double* u, double* f) {
 
 int eslb_step(eslb_ctx* c, double* f, int64_t nsteps) {
   if (!c || !f || nsteps < 0) return set_err(c, ESLB_ERR_INVALID_ARG, "bad argument to eslb_step");
+  if (nsteps > 0 && c->small_run && !c->track) return run_small(c, f, nsteps);
   for (int64_t s = 0; s < nsteps; ++s) {
     for (const Pass& ps : c->passes) {
       const int rc = run_pass(c, f, ps.shift, ps.op);

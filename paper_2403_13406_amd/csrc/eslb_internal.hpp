@@ -76,5 +76,6 @@ struct eslb_ctx {
   double* partials = nullptr;
   int diag_blocks = 0;
   int track = 0;
+  bool small_run = false;  // whole run in one workgroup's LDS (small states)
   std::string err;
 };

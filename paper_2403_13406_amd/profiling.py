@@ -3,6 +3,8 @@
     python -m paper_2403_13406_amd.profiling stats <kernel_stats.csv>
     python -m paper_2403_13406_amd.profiling traffic --fetch <fetch counter_collection.csv>
         --write <write counter_collection.csv> --kernel k_stage --copy-bytes N --workload TAG --out FILE.json
+    python -m paper_2403_13406_amd.profiling valu --csv <counter_collection.csv> --kernel k_stage
+        --nodes N --workload TAG --out FILE.json
 
 HBM traffic of a kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
 the kernel's dispatches, each scaled by known-bytes / counter-reading of a plain
@@ -92,6 +94,18 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes):
     }
 
 
+def valu(valu_csv, kernel, nodes):
+    """FP64 VALU instructions per node of a kernel (SQ_INSTS_VALU_*_F64 count wave instructions)."""
+    c = counters(valu_csv)
+    k = _pick(c, kernel)
+    mean = lambda v: sum(v) / len(v)
+    per = {name: mean(vals) * 64.0 / nodes for name, vals in c[k].items() if name.startswith("SQ_INSTS")}
+    flop = (per.get("SQ_INSTS_VALU_ADD_F64", 0.0) + per.get("SQ_INSTS_VALU_MUL_F64", 0.0)
+            + 2.0 * per.get("SQ_INSTS_VALU_FMA_F64", 0.0) + per.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
+    return {"kernel": k, "dispatches": len(next(iter(c[k].values()))), "nodes": nodes,
+            "lane_instructions_per_node": per, "fp64_flop_per_node": flop}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -104,7 +118,21 @@ def main(argv=None):
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--workload", required=True)
     t.add_argument("--out", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("--csv", required=True)
+    v.add_argument("--kernel", default="k_stage")
+    v.add_argument("--nodes", type=int, required=True)
+    v.add_argument("--workload", required=True)
+    v.add_argument("--out", required=True)
     a = ap.parse_args(argv)
+    if a.cmd == "valu":
+        rec = valu(a.csv, a.kernel, a.nodes)
+        rec["workload"] = a.workload
+        rec["source_hash"] = source_hash()
+        with open(a.out, "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(json.dumps(rec, indent=1))
+        return 0
     if a.cmd == "stats":
         print("%-100s %7s %14s %8s" % ("kernel", "calls", "avg_us", "pct"))
         for name, calls, avg, pct in kernel_stats(a.csv):

@@ -220,3 +220,39 @@ def test_fallback_and_errors():
     u[0, 0, 2] = -1.0
     with pytest.raises(EslbError):
         sw.init_equilibrium(to_gpu(u))
+
+
+@pytest.mark.parametrize("lattice,system,nx,ny,V,param,scheme", [
+    ("D1Q2", "burgers", 1024, 1, 2.0, (1.0,), 1),
+    ("D1Q2", "shallow_water", 1000, 1, 4.5, (9.81,), 1),
+    ("D2Q4", "burgers", 40, 31, 2.0, (1.0, 0.6), 1),
+    ("D2Q4", "shallow_water", 24, 20, 8.0, (9.81,), 1),
+    ("D2Q4", "euler", 16, 12, 3.2, (1.4,), 1),
+    ("D1Q2", "burgers", 640, 1, 2.0, (1.0,), 3),
+])
+def test_whole_run_in_lds_equals_pass_by_pass(lattice, system, nx, ny, V, param, scheme):
+    """States of at most 64 KiB run all passes in one workgroup's LDS; bits must equal the per-pass path."""
+    from paper_2403_13406_amd import Solver
+    lat, sys = oracle_system(lattice, system, param)
+    rng = np.random.default_rng(14)
+    if system == "burgers":
+        u = 0.3 + 0.02 * rng.standard_normal((1, ny, nx))
+    elif system == "shallow_water":
+        h = 1.0 + 0.01 * rng.standard_normal((ny, nx))
+        u = np.stack([h] + [0.01 * rng.standard_normal((ny, nx)) for _ in range(lat.d)])
+    else:
+        w = W.euler2d(nx, ny=ny)
+        u = w.initial_state()
+    runs = []
+    for track in (False, True):        # stats tracking forces one launch per pass
+        s = Solver(lattice, system, nx, ny, V=V, relax="entropic", scheme=scheme, param=param)
+        s.set_stats(track)
+        f = s.init_equilibrium(to_gpu(u))
+        s.transport(3)                 # start from unequal-to-zero offsets
+        s.step(f, 3)
+        s.sync()
+        runs.append((to_host(f), s.offsets, to_host(s.gather(f))))
+    assert runs[0][1] == runs[1][1]
+    assert np.array_equal(runs[0][0], runs[1][0])
+    want = run(Relaxer(lat, sys, V, "entropic"), transport(lat, equilibrium(lat, sys, V, u), 3), 3, scheme=scheme)
+    assert max(componentwise_error(runs[0][2], want)) <= PARITY_RTOL
