@@ -81,7 +81,10 @@ typedef struct eslb_problem {
   int32_t kappa;     /* >= 1                                                     */
   int32_t relax;     /* ESLB_OMEGA_FIXED or ESLB_OMEGA_ENTROPIC                  */
   int32_t scheme;    /* 1: Phi of eq. splittingToUse (Scheme I); 2, 3: Schemes II
-                        and III of Sec. 6.1 (projections R_1 added)              */
+                        and III of Sec. 6.1 (projections R_1 added); comparison
+                        schedules: 4: standard LB (R T(dt/24))^24 (Sec. 3.1);
+                        5: Scheme (A) R T(dt), dt = kappa dx/V; 6: Scheme (B)
+                        R_1 T(dt/4) R T(dt/2) R T(dt/4), dt = 4 kappa dx/V (Sec. 6.3) */
   int32_t reserved;  /* must be 0                                                */
   double V;          /* kinetic velocity, > 0                                    */
   double dx;         /* space step, > 0                                          */
@@ -115,7 +118,8 @@ int eslb_state_bytes(const eslb_ctx* ctx, size_t* bytes);
 /* Number of conserved components M and of velocities q. */
 int eslb_dims(const eslb_ctx* ctx, int32_t* M, int32_t* q);
 
-/* Delta t = 24 kappa dx / V (Sec. 2.3). */
+/* Delta t of one step = (cells moved per step) dx / V: 24 kappa dx / V for
+ * schemes 1-4 (Sec. 2.3), kappa dx / V for 5, 4 kappa dx / V for 6. */
 int eslb_dt(const eslb_ctx* ctx, double* dt);
 /* n = floor(T / Delta t) in binary64 (the paper leaves this open); returns
  * ESLB_WARN_T_NOT_MULTIPLE when n * Delta t != T. */

@@ -91,3 +91,15 @@ def run(relax, f, nsteps, kappa=1, scheme=1, callback=None):
 def moments(f):
     """u = sum_k f_k (Sec. 1.2); meaningful at step boundaries (Sec. 2.3, cost remark)."""
     return f.sum(axis=0)
+
+
+def scheme_A_step(relax, f, kappa=1):
+    """Scheme (A) of Sec. 6.3: R T(dt), dt = kappa dx / V (omega chosen by the caller)."""
+    return relax(transport(relax.lat, f, kappa))
+
+
+def scheme_B_step(relax, f, kappa=1):
+    """Scheme (B) of Sec. 6.3: R_1 T(dt/4) R T(dt/2) R T(dt/4), dt = 4 kappa dx / V."""
+    f = relax(transport(relax.lat, f, kappa))
+    f = relax(transport(relax.lat, f, 2 * kappa))
+    return relax.project(transport(relax.lat, f, kappa))

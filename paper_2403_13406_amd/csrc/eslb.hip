@@ -570,7 +570,7 @@ int validate_problem(const eslb_problem* p, std::string& why, int* kind, int* d,
     why = "fixed omega must lie in (0, 2]";
     return ESLB_ERR_INVALID_ARG;
   }
-  if (p->scheme < 1 || p->scheme > 3) { why = "scheme must be 1, 2 or 3"; return ESLB_ERR_INVALID_ARG; }
+  if (p->scheme < 1 || p->scheme > 6) { why = "scheme must be 1..6"; return ESLB_ERR_INVALID_ARG; }
   if (p->reserved != 0) { why = "reserved must be 0"; return ESLB_ERR_INVALID_ARG; }
   if (p->system == ESLB_SHALLOW_WATER && !(p->param[0] > 0.0)) { why = "shallow water needs g > 0"; return ESLB_ERR_INVALID_ARG; }
   if (p->system == ESLB_EULER && !(p->param[0] > 1.0)) { why = "Euler needs gamma > 1"; return ESLB_ERR_INVALID_ARG; }
@@ -603,6 +603,26 @@ void build_schedule(eslb_ctx* c) {
       c->passes.push_back({2 * s, PASS_RELAX});
       c->passes.push_back({s, PASS_PROJECT});
     }
+    c->trailing = 0;
+    return;
+  }
+  if (c->pb.scheme == 4) {
+    // standard second-order LB at the same cost (Sec. 3.1, fair comparison): (R T(dt/24))^24
+    for (int i = 0; i < 24; ++i) c->passes.push_back({k, PASS_RELAX});
+    c->trailing = 0;
+    return;
+  }
+  if (c->pb.scheme == 5) {
+    // Scheme (A) of Sec. 6.3: R T(dt), dt = kappa dx / V
+    c->passes.push_back({k, PASS_RELAX});
+    c->trailing = 0;
+    return;
+  }
+  if (c->pb.scheme == 6) {
+    // Scheme (B) of Sec. 6.3: R_1 T(dt/4) R T(dt/2) R T(dt/4), dt = 4 kappa dx / V
+    c->passes.push_back({k, PASS_RELAX});
+    c->passes.push_back({2 * k, PASS_RELAX});
+    c->passes.push_back({k, PASS_PROJECT});
     c->trailing = 0;
     return;
   }
@@ -793,15 +813,19 @@ int eslb_dims(const eslb_ctx* c, int32_t* M, int32_t* q) {
   return ESLB_OK;
 }
 
+// Delta t of one step: the cells every population moves per step, times dx / V
+// (24 kappa dx / V for the fourth-order schemes, Sec. 2.3).
+static double step_dt(const eslb_ctx* c) { return (double)net_shift(c) * c->pb.dx / c->pb.V; }
+
 int eslb_dt(const eslb_ctx* c, double* dt) {
   if (!c || !dt) return ESLB_ERR_INVALID_ARG;
-  *dt = 24.0 * c->pb.kappa * c->pb.dx / c->pb.V;
+  *dt = step_dt(c);
   return ESLB_OK;
 }
 
 int eslb_steps_for_time(const eslb_ctx* c, double T, int64_t* n) {
   if (!c || !n || !(T >= 0.0) || !std::isfinite(T)) return ESLB_ERR_INVALID_ARG;
-  const double dt = 24.0 * c->pb.kappa * c->pb.dx / c->pb.V;
+  const double dt = step_dt(c);
   const double r = std::floor(T / dt);
   *n = (int64_t)r;
   return (r * dt == T) ? ESLB_OK : ESLB_WARN_T_NOT_MULTIPLE;

@@ -256,3 +256,26 @@ def test_whole_run_in_lds_equals_pass_by_pass(lattice, system, nx, ny, V, param,
     assert np.array_equal(runs[0][0], runs[1][0])
     want = run(Relaxer(lat, sys, V, "entropic"), transport(lat, equilibrium(lat, sys, V, u), 3), 3, scheme=scheme)
     assert max(componentwise_error(runs[0][2], want)) <= PARITY_RTOL
+
+
+@pytest.mark.parametrize("scheme", [4, 5, 6])
+@pytest.mark.parametrize("relax", ["fixed", "entropic"])
+def test_comparison_schedules(scheme, relax):
+    """Standard LB comparator (Sec. 3.1) and Schemes (A), (B) of Sec. 6.3, on 2D Euler and 1D Burgers."""
+    from oracle.scheme import scheme_A_step, scheme_B_step, standard_lb_step
+    step = {4: standard_lb_step, 5: scheme_A_step, 6: scheme_B_step}[scheme]
+    for w in (W.euler2d(70, ny=37), W.burgers1d(3000)):
+        lat, sys = oracle_system(w.lattice, w.system, w.param)
+        u = w.initial_state()
+        omega = 1.93 if (scheme == 5 and relax == "fixed") else 2.0
+        s = solver_for(w, relax, scheme=scheme, omega=omega)
+        f = s.init_equilibrium(to_gpu(u))
+        s.step(f, 3)
+        assert s.sync() == 0
+        r = Relaxer(lat, sys, w.V, relax, omega)
+        want = equilibrium(lat, sys, w.V, u)
+        for _ in range(3):
+            want = step(r, want)
+        assert max(componentwise_error(to_host(s.gather(f)), want)) <= PARITY_RTOL
+        net = {4: 24, 5: 1, 6: 4}[scheme]
+        assert abs(s.dt() - net * w.dx / w.V) <= 1e-15 * s.dt()
