@@ -44,6 +44,37 @@ __device__ __forceinline__ long long storage_index(const Grid& g, int k, int x, 
   return (long long)ys * g.nx + x;
 }
 
+// Planes of at most 2^29 nodes: byte offsets within a plane fit 32 bits, and
+// with the plane base wave-uniform the accesses take the scalar-base +
+// 32-bit-offset form (no per-lane 64-bit address arithmetic).
+constexpr long long kPlane32 = 1ll << 29;
+
+template <int D>
+__device__ __forceinline__ unsigned storage_offset32(const Grid& g, int k, int x, int y) {
+  int xs = x, ys = y;
+  if (Lat<D>::axis(k) == 0) {
+    xs += g.sh[k];
+    if (xs >= g.nx) xs -= g.nx;
+  } else {
+    ys += g.sh[k];
+    if (ys >= g.ny) ys -= g.ny;
+  }
+  return ((unsigned)ys * (unsigned)g.nx + (unsigned)xs) * 8u;
+}
+
+// Base pointers of the q M planes, computed on the host (kernel arguments live
+// in scalar registers).  The empty asm keeps each base opaque: left visible,
+// the compiler folds the plane offsets into per-lane 64-bit adds.
+struct Planes {
+  double* p[16];
+};
+
+__device__ __forceinline__ double* opaque_base(double* b) { return b; }
+
+__device__ __forceinline__ double& plane_at(double* base, unsigned byte_off) {
+  return *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 __device__ __forceinline__ void record_flags(DevStats* st, unsigned flags) {
   if (flags) {
     atomicOr(&st->flags, flags);
@@ -64,11 +95,12 @@ __device__ __forceinline__ void record_omega(DevStats* st, bool act, double om) 
   }
 }
 
-// One relaxation pass (the shift that precedes it is in g.sh).
-template <class S, int D>
+// One relaxation pass (the shift that precedes it is in g.sh).  Off32: planes
+// of at most kPlane32 nodes (32-bit byte offsets); otherwise 64-bit indices.
+template <class S, int D, bool Off32>
 // two waves per SIMD: fewer registers than the unconstrained build (one wave) but
 // no real spilling; measured 1.40x faster on the Euler stage
-__global__ __launch_bounds__(256, 2) void k_stage(Grid g, Phys P, int mode, int track, DevStats* st) {
+__global__ __launch_bounds__(256, 2) void k_stage(Grid g, Planes pl, Phys P, int mode, int track, DevStats* st) {
   constexpr int Q = S::Q, M = S::M;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -76,23 +108,41 @@ __global__ __launch_bounds__(256, 2) void k_stage(Grid g, Phys P, int mode, int 
   unsigned flags = 0;
   double om = 2.0;
   if (act) {
-    long long id[Q];
     double f[Q][M];
-#pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      id[k] = storage_index<D>(g, k, x, y);
-#pragma unroll
-      for (int m = 0; m < M; ++m) f[k][m] = g.f[(long long)(k * M + m) * g.plane + id[k]];
-    }
-    om = relax_node<S>(f, mode, P, flags);
     bool fin = true;
+    if constexpr (Off32) {
+      unsigned off[Q];
 #pragma unroll
-    for (int k = 0; k < Q; ++k)
+      for (int k = 0; k < Q; ++k) {
+        off[k] = storage_offset32<D>(g, k, x, y);
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
-        fin &= isfinite(f[k][m]);
-        g.f[(long long)(k * M + m) * g.plane + id[k]] = f[k][m];
+        for (int m = 0; m < M; ++m) f[k][m] = plane_at(opaque_base(pl.p[k * M + m]), off[k]);
       }
+      om = relax_node<S>(f, mode, P, flags);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          fin &= isfinite(f[k][m]);
+          plane_at(opaque_base(pl.p[k * M + m]), off[k]) = f[k][m];
+        }
+    } else {
+      long long id[Q];
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        id[k] = storage_index<D>(g, k, x, y);
+#pragma unroll
+        for (int m = 0; m < M; ++m) f[k][m] = g.f[(long long)(k * M + m) * g.plane + id[k]];
+      }
+      om = relax_node<S>(f, mode, P, flags);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          fin &= isfinite(f[k][m]);
+          g.f[(long long)(k * M + m) * g.plane + id[k]] = f[k][m];
+        }
+    }
     if (!fin) flags |= FLAG_NAN;
   }
   record_flags(st, flags);
@@ -523,9 +573,17 @@ int launch_stage(eslb_ctx* c, double* f, int mode) {
   launch_shape(c, grid, block);
   const int track = (mode == 1) ? c->track : 0;
   Phys P = c->phys;
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D>), grid, block, 0, c->stream, g, P, mode, track, c->st)
-  ESLB_DISPATCH(c->kind, CALL)
+  Planes pl{};
+  for (int i = 0; i < c->q * c->M; ++i) pl.p[i] = f + (long long)i * g.plane;
+  if (g.plane <= kPlane32) {
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st)
+    ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
+  } else {
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st)
+    ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  }
   return hip_check(c, hipGetLastError(), "stage kernel launch");
 }
 
@@ -587,6 +645,8 @@ Phys make_phys(const eslb_problem& p, int q) {
   P.p1 = p.param[1];
   P.p2 = (p.system == ESLB_EULER) ? 1.0 / (p.param[0] - 1.0) : 0.0;
   P.omega = p.omega;
+  P.V2 = 2.0 * p.V;
+  P.q0 = (p.system == ESLB_EULER) ? -p.V * (p.param[0] + 1.0) / (p.param[0] - 1.0) : 0.0;
   return P;
 }
 

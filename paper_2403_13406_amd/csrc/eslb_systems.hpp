@@ -33,50 +33,57 @@ struct Phys {
   double p0, p1; // system parameters (a_x,a_y | b_x,b_y | g | gamma)
   double p2;     // derived: 1/(gamma-1) for Euler
   double omega;  // fixed relaxation parameter
+  double V2;     // 2V
+  double q0;     // derived: -V (gamma+1)/(gamma-1) for Euler
 };
 
-// Reciprocal from the hardware estimate refined by two Newton steps
-// r <- r (2 - x r) (each squares the relative error; about 1 ulp at the end).
+// Reciprocal from the hardware estimate (relative error below 2^-24 on gfx950,
+// measured) refined by one third-order step: with e = 1 - x r,
+// r <- r (1 + e + e^2) leaves e^3 < 2^-72, so the result is within rounding.
 // Arguments here are O(1) positive or negative normal numbers.
 __device__ __forceinline__ double rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
-// sqrt of a positive normal number: hardware rsq estimate, two Goldschmidt
-// refinements of (sqrt x, 1/(2 sqrt x)) and a final residual correction.
+// sqrt of a positive normal number: hardware rsq estimate (relative error below
+// 2^-24), one Goldschmidt refinement of (sqrt x, 1/(2 sqrt x)) (error ~2^-48)
+// and a final residual correction s + (x - s^2)/(2 sqrt x) (error ~2^-96).
 __device__ __forceinline__ double sqrt_pos(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   double s = x * y, h = 0.5 * y;
-  double r = fma(-s, h, 0.5);
-  s = fma(s, r, s);
-  h = fma(h, r, h);
-  r = fma(-s, h, 0.5);
+  const double r = fma(-s, h, 0.5);
   s = fma(s, r, s);
   h = fma(h, r, h);
   const double d = fma(-s, s, x);
   return fma(d, h, s);
 }
 
-// log(1 + z).  For |z| < 1/128 (the increments near equilibrium) the Taylor
-// series to z^9 (truncation below 1e-19 relative); otherwise the library log1p.
-__device__ __forceinline__ double log1p_near0(double z) {
-  if (fabs(z) < 0.0078125) {
-    double p = 1.0 / 9.0;
-    p = fma(p, z, -1.0 / 8.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, -1.0 / 6.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, -0.25);
-    p = fma(p, z, 1.0 / 3.0);
-    p = fma(p, z, -0.5);
-    p = fma(p, z, 1.0);
-    return p * z;
+// phi(z) = z - log1p(z) for a pair of arguments.  For |z| < 2^-7 (increments
+// near equilibrium) phi(z) = z^2 g(z) with g(z) = sum_j (-1)^j z^j / (j + 2)
+// replaced by its Chebyshev-economised degree-6 polynomial on [-2^-7, 2^-7]
+// (relative error below 2^-52 in binary64; no cancellation between z and
+// log1p(z)); otherwise z - log1p(z) with the library log1p for both.
+__device__ __forceinline__ double phi_poly(double z) {
+  double g = 0.12501220790442075;
+  g = fma(g, z, -0.14286901156622775);
+  g = fma(g, z, 0.16666666620096096);
+  g = fma(g, z, -0.199999999637788);
+  g = fma(g, z, 0.25000000000000566);
+  g = fma(g, z, -0.3333333333333361);
+  g = fma(g, z, 0.5);
+  return (z * z) * g;
+}
+
+__device__ __forceinline__ void phi_pair(double za, double zb, double& pa, double& pb) {
+  if ((fabs(za) < 0.0078125) & (fabs(zb) < 0.0078125)) {
+    pa = phi_poly(za);
+    pb = phi_poly(zb);
+  } else {
+    pa = za - log1p(za);
+    pb = zb - log1p(zb);
   }
-  return log1p(z);
 }
 
 template <int D> struct Lat;
@@ -277,7 +284,7 @@ struct Euler2 {
   static constexpr int D = 2, M = 4, Q = 4;
   struct Node { double rho, vel[2], p, E, irho, ip; };
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
-    const double rho = u[0], ir = 1.0 / rho;
+    const double rho = u[0], ir = rcp(rho);
     const double vx = u[1] * ir, vy = u[2] * ir;
     const double p = (P.p0 - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
     const double uj = j == 0 ? vx : vy;
@@ -289,13 +296,13 @@ struct Euler2 {
   }
   __device__ static bool prepare(const double* u, Node& c, const Phys& P) {
     c.rho = u[0];
-    const double ir = 1.0 / u[0];
+    const double ir = rcp(u[0]);
     c.vel[0] = u[1] * ir;
     c.vel[1] = u[2] * ir;
     c.E = u[3];
     c.p = (P.p0 - 1.0) * (u[3] - 0.5 * u[0] * (c.vel[0] * c.vel[0] + c.vel[1] * c.vel[1]));
     c.irho = ir;
-    c.ip = 1.0 / c.p;
+    c.ip = rcp(c.p);
     return (c.rho > 0.0) && (c.p > 0.0);
   }
   __device__ static bool subchar(const Node& c, const Phys& P) {
@@ -328,16 +335,18 @@ struct Euler2 {
   // With e = t d, the increment quadratic simplifies (the 2V x_1 u_n terms cancel):
   //   qa = -V x_1 (gamma+1)/(gamma-1),
   //   qb = sigma (gamma (t P0c + p) - 2V x_1 W)/(gamma-1),
-  //   qc = t (qc1 + V dtn (2 u_t + du_t)),
+  //   qc = t (qc1 + V dtn (2 u_t + du_t)),  du_t = t dtn / x_1,
   // with per-velocity constants gnd = d_n - u_n d_1, dtn = d_t - u_t d_1,
-  // P0c = 2 sigma V gnd, qc1 = -2V d_E + V d_1 |u|^2 + P0c (W/(gamma-1) + sigma u_n),
-  // which do not depend on t and are hoisted out of the root iteration.
+  // P0c = 2 sigma V gnd, qc1 = -2V d_E + V d_1 |u|^2 + P0c (W/(gamma-1) + sigma u_n).
+  // Multiplied through by x_1 (qa/x_1 = q0 is a constant, qcx = x_1 qc has no
+  // division), the quadratic needs one reciprocal, 1/(x_1 den), for both dn and
+  // du_t.
   template <int k, bool DV>
   __device__ static bool bregman(const Node& c, const double* feq, const double* d, double t, double& B, double* dv,
                                  const Phys& P) {
     constexpr int n = Lat<2>::axis(k), tt = 1 - n;
     constexpr double s = Lat<2>::sign(k);
-    const double gm = P.p0, igm1 = P.p2, V = P.V;
+    const double gm = P.p0, igm1 = P.p2, V = P.V, V2 = P.V2;
     const double rho = c.rho, p = c.p, un = c.vel[n], ut = c.vel[tt];
     const double W = P.W0 + s * un;
     const double f1 = feq[0];
@@ -348,33 +357,39 @@ struct Euler2 {
     asm volatile("" : "+v"(d0), "+v"(dn_), "+v"(dt_), "+v"(d3));
     const double gnd = dn_ - un * d0;
     const double dtn = dt_ - ut * d0;
-    const double P0c = 2.0 * V * s * gnd;
-    const double qc1 = -2.0 * V * d3 + V * d0 * (un * un + ut * ut) + P0c * (W * igm1 + s * un);
+    const double P0c = s * V2 * gnd;
+    const double qc1 = -V2 * d3 + V * d0 * (un * un + ut * ut) + P0c * (W * igm1 + s * un);
     // t-dependent part
     const double e1 = t * d0;
     const double x1 = f1 + e1;
-    const double dt = t * dtn * rcp(x1);
-    const double qa = -V * x1 * (gm + 1.0) * igm1;
-    const double qb = s * igm1 * (gm * (t * P0c + p) - 2.0 * V * x1 * W);
-    const double qc = t * (qc1 + V * dtn * (2.0 * ut + dt));
-    const double disc = qb * qb - 4.0 * qa * qc;
+    const double tdtn = t * dtn;
+    const double qb = s * igm1 * (gm * (t * P0c + p) - V2 * x1 * W);
+    const double qcx = t * (qc1 * x1 + V * dtn * (2.0 * ut * x1 + tdtn));
+    const double disc = qb * qb - 4.0 * P.q0 * qcx;
     const bool okd = disc > 0.0;
     const double den = qb + copysign(okd ? sqrt_pos(disc) : 0.0, qb);
-    const double dn = -2.0 * qc * rcp(den);
-    const double dp = t * P0c - 2.0 * V * s * x1 * dn;
+    const double r1 = rcp(x1 * den);
+    const double dn = -2.0 * qcx * r1;
+    const double dt = tdtn * den * r1;
+    const double dp = t * P0c - s * V2 * x1 * dn;
     const double Wp = W + s * dn;
-    const double drho = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
+    const double drho = V2 * (e1 * W - s * f1 * dn) * rcp(W * Wp);
     const double rhop = rho + drho, pp = p + dp;
     const double al = dp * c.ip, be = drho * c.irho;
     const double opa = 1.0 + al, opb = 1.0 + be;
     const double rab = rcp(opa * opb);
     const double ibb = opa * rab;  // 1/(1+be)
-    const double ds = log1p_near0(al) - gm * log1p_near0(be);
+    // za = (1+al)/(1+be) - 1, zb = 1/(1+be) - 1: the thermal part of B is
+    // x_1 [phi(za)/(gamma-1) + phi(zb)], and ds = log1p(al) - gamma log1p(be)
+    // = log1p(za) + (gamma-1) log1p(zb)
+    const double za = (al - be) * ibb, zb = -be * ibb;
+    double pa, pb;
+    phi_pair(za, zb, pa, pb);
     const double du2 = dn * dn + dt * dt;
-    B = x1 * (((al - be) * ibb - ds) * igm1 - be * ibb) + 0.5 * rho * x1 * du2 * c.ip +
-        s * rho * dp * dn * c.ip * P.inv2V;
+    B = x1 * fma(pa, igm1, pb) + 0.5 * rho * x1 * du2 * c.ip + s * rho * dp * dn * c.ip * P.inv2V;
     if (DV) {
       // entropy-variable difference v(U_k) - v(u)
+      const double ds = (za - pa) + (gm - 1.0) * (zb - pb);
       const double bet = rho * c.ip;
       const double dbet = bet * (be - al) * (opb * rab);
       const double unp = un + dn, utp = ut + dt;
@@ -385,7 +400,8 @@ struct Euler2 {
       dv[1 + tt] = dbet * utp + bet * dt;
       dv[3] = -dbet;
     }
-    return okd && (x1 > 0.0) && (Wp > 0.0) && (rhop > 0.0) && (pp > 0.0) && (rhop * Wp * Wp > gm * pp) && isfinite(B);
+    // all conditions evaluated (no short-circuit branches)
+    return okd & (x1 > 0.0) & (Wp > 0.0) & (rhop > 0.0) & (pp > 0.0) & (rhop * Wp * Wp > gm * pp) & isfinite(B);
   }
 };
 
@@ -433,7 +449,10 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&f
   }
 }
 
-// u = sum_k f_k, f^eq(u), d = f - f^eq and the scales used by the stop rule.
+// u = sum_k f_k, f^eq(u), d = f - f^eq and the scales used by the stop rule:
+// dmax = max |d| and fsc = max |f^eq| + dmax, an upper bound of max(|f^eq|, |f|)
+// within a factor 2 (maxima of computed values need no NaN canonicalisation,
+// those of the loaded f would).
 template <class S>
 __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double (&u)[S::M],
                                            double (&feq)[S::Q][S::M], double (&d)[S::Q][S::M], double& dmax,
@@ -448,15 +467,16 @@ __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double
   }
   Eq<S>::equilibrium(u, feq, P);
   dmax = 0.0;
-  fsc = 0.0;
+  double femax = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       d[k][m] = f[k][m] - feq[k][m];
       dmax = fmax(dmax, fabs(d[k][m]));
-      fsc = fmax(fsc, fmax(fabs(feq[k][m]), fabs(f[k][m])));
+      femax = fmax(femax, fabs(feq[k][m]));
     }
+  fsc = femax + dmax;
 }
 
 // lambda = omega - 1 solving F(-lambda) = F(1) (eq. variableOmegaProblem in the
@@ -494,27 +514,28 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
     } else {
       lo = 1.0;
     }
-    double xn = okm ? 1.0 + H / dFm : NAN;  // Newton from lambda = 1 (H' = -F'(-1))
+    double xn = okm ? 1.0 + H * rcp(dFm) : NAN;  // Newton from lambda = 1 (H' = -F'(-1))
     if (okm) {
       const double G1 = F1, Gm = Fm, G1p = dF1 - 2.0 * F1, Gmp = dFm + 2.0 * Fm;
       const double cc = 0.25 * (G1p - Gmp);
       const double dd = 0.25 * ((G1p + Gmp) - (G1 - Gm));
       const double bb = 0.5 * (G1 - Gm) - dd;
       const double aa = 0.5 * (G1 + Gm) - cc;
-      double lp = 1.0, pd = 1.0;
+      double lp = 1.0, pd = 1.0, rpd = 1.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const double g = aa + lp * (-bb + lp * (cc - dd * lp));
         const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
         const double pv = lp * lp * g - G1;
         pd = 2.0 * lp * g + lp * lp * gp;
-        lp -= pv / pd;
+        rpd = rcp(pd);
+        lp -= pv * rpd;
       }
       if (isfinite(lp) && lp > lo && lp < hi && pd > 0.0) {
         double F3 = 0.0, dF3 = 0.0;
         const bool ok3 = fsum<S, false>(c, feq, d, -lp, F3, dF3, P);
         const double H3 = F3 - F1;
-        const double xc = lp - H3 / pd;
+        const double xc = lp - H3 * rpd;
         if (ok3 && isfinite(xc) && fabs(xc - lp) * dmax <= tol) return xc;
         if (!ok3 || H3 > 0.0) {
           if (lp <= hi) { hi = lp; hi_bad = !ok3; }
