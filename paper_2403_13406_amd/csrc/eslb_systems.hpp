@@ -595,13 +595,19 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
   typename S::Node c;
   const bool adm = S::prepare(u, c, P);
   if (!adm) flags |= FLAG_INADMISSIBLE;
-  if (dmax == 0.0) return 2.0;  // at equilibrium: omega = 2 (limit of the root)
-  bool fallback = !adm;
-  double lam = 0.0;
-  if (adm) lam = entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback);
-  if (fallback) {
+  // At equilibrium (d = 0, so f = f^eq exactly) omega = 2, the limit of the
+  // root; the common update below then returns f^eq = f, so f itself need not
+  // stay live through the root iteration.
+  bool fallback = false;
+  double lam = 1.0;
+  if (dmax != 0.0) {
+    fallback = !adm;
     lam = 0.0;
-    flags |= FLAG_FALLBACK;
+    if (adm) lam = entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback);
+    if (fallback) {
+      lam = 0.0;
+      flags |= FLAG_FALLBACK;
+    }
   }
   // The root iteration only reads the mass component of each f^eq_k; rebuilding
   // f^eq from u here (rather than keeping all q*M values live through the
