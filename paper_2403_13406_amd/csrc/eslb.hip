@@ -62,14 +62,13 @@ __device__ __forceinline__ unsigned storage_offset32(const Grid& g, int k, int x
   return ((unsigned)ys * (unsigned)g.nx + (unsigned)xs) * 8u;
 }
 
-// Base pointers of the q M planes, computed on the host (kernel arguments live
-// in scalar registers).  The empty asm keeps each base opaque: left visible,
-// the compiler folds the plane offsets into per-lane 64-bit adds.
+// Base pointers of the q M planes, computed on the host.  Kernel arguments
+// live in scalar registers, and as independent pointers (rather than one base
+// plus plane multiples, which the compiler folds into per-lane 64-bit adds)
+// each access keeps the scalar-base + 32-bit-offset form.
 struct Planes {
   double* p[16];
 };
-
-__device__ __forceinline__ double* opaque_base(double* b) { return b; }
 
 __device__ __forceinline__ double& plane_at(double* base, unsigned byte_off) {
   return *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off);
@@ -116,7 +115,7 @@ __global__ __launch_bounds__(256, 2) void k_stage(Grid g, Planes pl, Phys P, int
       for (int k = 0; k < Q; ++k) {
         off[k] = storage_offset32<D>(g, k, x, y);
 #pragma unroll
-        for (int m = 0; m < M; ++m) f[k][m] = plane_at(opaque_base(pl.p[k * M + m]), off[k]);
+        for (int m = 0; m < M; ++m) f[k][m] = plane_at(pl.p[k * M + m], off[k]);
       }
       om = relax_node<S>(f, mode, P, flags);
 #pragma unroll
@@ -124,7 +123,7 @@ __global__ __launch_bounds__(256, 2) void k_stage(Grid g, Planes pl, Phys P, int
 #pragma unroll
         for (int m = 0; m < M; ++m) {
           fin &= isfinite(f[k][m]);
-          plane_at(opaque_base(pl.p[k * M + m]), off[k]) = f[k][m];
+          plane_at(pl.p[k * M + m], off[k]) = f[k][m];
         }
     } else {
       long long id[Q];
