@@ -231,16 +231,24 @@ template <int D> struct ShallowWater {
     const double x1 = f1 + e1;
     const double gn = t * (d[1 + n] - d[0] * un);
     const double W2 = W * W;
-    double dn = 0.0;
+    // The cubic in monomial form P0 + P1 dn + P2 dn^2 + P3 dn^3 (with a = sigma f1,
+    // A = a dn - e1 W, Bq = (f1 + x1) W + a dn, C = gn - x1 dn, Dq = W^2 W'^2);
+    // P0 = O(e), P1 = f1 W^2 (g h - W^2) + O(e) < 0 in the sub-characteristic range.
+    const double gV = s * g * V;
+    const double a = s * f1, b = -e1 * W, cq = (f1 + x1) * W;
+    const double P0 = gV * b * cq + gn * W2 * W2;
+    const double P1 = gV * a * (b + cq) + W2 * W * (2.0 * s * gn - x1 * W);
+    const double P2 = gV * a * a + W2 * (gn - 2.0 * s * x1 * W);
+    const double P3 = -x1 * W2;
+    // start from the second-order series reversion of the root about dn = 0,
+    // -P0/P1 - P2 P0^2/P1^3 (error O(dn^3)), then Newton
+    const double rP1 = rcp(P1);
+    const double d0 = -P0 * rP1;
+    double dn = d0 * (1.0 - P2 * d0 * rP1);
 #pragma unroll 1
     for (int it = 0; it < 12; ++it) {
-      const double Wp = W + s * dn;
-      const double A = s * dn * f1 - e1 * W;
-      const double Bq = f1 * Wp + x1 * W;
-      const double C = gn - x1 * dn;
-      const double Dq = W2 * Wp * Wp;
-      const double Pv = s * g * V * A * Bq + C * Dq;
-      const double dP = g * V * f1 * (Bq + A) - x1 * Dq + 2.0 * s * C * W2 * Wp;
+      const double Pv = P0 + dn * (P1 + dn * (P2 + dn * P3));
+      const double dP = P1 + dn * (2.0 * P2 + 3.0 * P3 * dn);
       const double st = Pv * rcp(dP);
       dn -= st;
       // quadratic convergence: once a step is below 2^-40 |dn| the error left is ~2^-80 |dn|
