@@ -181,7 +181,7 @@ template <int D> struct ShallowWater {
   struct Node { double h, vel[D]; };
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
     const double h = u[0];
-    const double uj = u[1 + j] / h;
+    const double uj = u[1 + j] * rcp(h);
     phi[0] = u[1 + j];
 #pragma unroll
     for (int i = 0; i < D; ++i) phi[1 + i] = u[1 + i] * uj;
@@ -189,7 +189,7 @@ template <int D> struct ShallowWater {
   }
   __device__ static bool prepare(const double* u, Node& c, const Phys&) {
     c.h = u[0];
-    const double ih = 1.0 / u[0];
+    const double ih = rcp(u[0]);
 #pragma unroll
     for (int i = 0; i < D; ++i) c.vel[i] = u[1 + i] * ih;
     return u[0] > 0.0;
