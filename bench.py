@@ -9,16 +9,24 @@ seeded synthetic smooth fields resident in HBM before timing starts.
 
 One JSON line:
   value        cells * K / timed seconds / 1e6 (MLUPS, whole job, one GPU)
-  roofline     the stage kernel: algorithmic bytes per launch (2 q M 8 B per node)
-               / its average launch time (HIP events on the solver's stream around
-               the timed steps, which hold stage kernels only) vs 8 TB/s;
-               traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated
-               on a plain copy), from profiles/ when the kernel sources still match
+  roofline     the stage kernel, timed with HIP events on the solver's stream
+               around the timed steps (stage kernels only).  When profiles/ holds a
+               VALU counter record of the same kernel sources, "bound": "alu":
+               FP64 FLOPs per node (ADD + MUL + 2 FMA + TRANS lane instructions)
+               x nodes per launch / average launch time vs 78.6 TFLOP/s; otherwise
+               the HBM figure below.
+  hbm          algorithmic bytes per launch (2 q M 8 B per node) / average launch
+               time vs 8 TB/s; traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per
+               launch (calibrated on a plain copy), from profiles/ when the kernel
+               sources still match
   cpu_baseline the CPU oracle, single-threaded, on a bounded sample of the workload
   batch        (default run) a reduced sample of the batched ensemble: one
                persistent-kernel batch run vs the plain per-instance loop, same GPU
   adjoint      (default run) forward vs forward+adjoint with checkpointing on the
                1024^2 Euler grid, same GPU
+  riemann      (default run) schemes (A), (B), (C) of Sec. 6.3 on the 2D Euler
+               four-state Riemann problem to T = 0.25 at 1024^2 and 2048^2, wall
+               seconds, with the paper's own (other GPU) times beside them
 --workload batch / adjoint run those two comparisons at their full sizes instead.
 """
 import argparse
@@ -270,6 +278,40 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
     return rec
 
 
+# wall times of the three schemes of Sec. 6.3 on the paper's GPU (other hardware:
+# context, not a target), seconds to T = 0.25
+RIEMANN_PAPER_S = {1024: {"A": 7.213, "B": 6.072, "C": 9.470}, 2048: {"A": 59.697, "B": 53.270, "C": 64.529}}
+
+
+def riemann_compare(torch, sizes=(1024, 2048)):
+    """Sec. 6.3 timing: schemes (A), (B), (C) on the 2D Euler Riemann problem to T = 0.25."""
+    from paper_2403_13406_amd import Solver
+    from paper_2403_13406_amd import workloads as W
+    out = {}
+    for n in sizes:
+        w = W.riemann2d(n)
+        u0 = torch.from_numpy(w.initial_state()).cuda()
+        row = {}
+        for name, opts in W.RIEMANN_SCHEMES.items():
+            s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, param=w.param, **opts)
+            f = s.init_equilibrium(u0)
+            steps = s.steps_for_time(w.extra["T"])
+            s.sync()
+            t0 = time.perf_counter()
+            s.step(f, steps)
+            s.sync()
+            sec = time.perf_counter() - t0
+            d = s.diagnostics(f)
+            row[name] = {"steps": steps, "seconds": round(sec, 4), "finite": d["n_nan"] == 0,
+                         "paper_seconds": RIEMANN_PAPER_S.get(n, {}).get(name)}
+            del f
+            progress("riemann %d^2: scheme %s, %d steps, %.3f s" % (n, name, steps, sec))
+        out["%dx%d" % (n, n)] = row
+        del u0
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,7 +320,8 @@ def main():
     ap.add_argument("--workload", default="euler2d")
     ap.add_argument("--size", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the reduced batch/adjoint comparisons")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reduced batch/adjoint comparisons and the Riemann-problem scheme timings")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
     ap.add_argument("--batch-steps-scale", type=float, default=1.0)
     ap.add_argument("--fd-dirs", type=int, default=0)
@@ -313,6 +356,8 @@ def main():
         rec["batch"] = batch_compare(torch, 48, 0.05)
         torch.cuda.empty_cache()
         rec["adjoint"] = adjoint_compare(torch, 1024, 100, 50)
+        torch.cuda.empty_cache()
+        rec["riemann"] = riemann_compare(torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(rec), flush=True)

@@ -21,6 +21,14 @@ sw2d_batch  512 instances of 2D shallow water, D2Q4^3; for instance i, rng(1000+
             g = 9.81, V = 8, h = 1 + 0.05 P_h, hu = 0.02 P_u, hv = 0.02 P_v, |k| <= 4.
 euler2d_adjoint  2D Euler at 1024^2, V = 3.2, amplitude 0.005, 2000 steps; target
             state from seed 1; finite-difference directions from seed 2.
+riemann2d   2D Euler four-quadrant Riemann problem (Sec. 6.3 setting: gamma = 1.4,
+            V = 6.21, T = 0.25, 1024^2 or 2048^2), constant states (rho, u, v, p)
+            split at x = 1/2, y = 1/2:  x>1/2,y>1/2: (1, 0, 0, 1);  x<1/2,y>1/2:
+            (0.6, 0.3, 0, 0.5);  x<1/2,y<1/2: (1, 0.3, 0.3, 1);  x>1/2,y<1/2:
+            (0.6, 0, 0.3, 0.5).  Our own states, symmetric about the diagonal, with
+            flows converging on the upper-right quadrant; they stand in for the
+            configuration of the cited Riemann-problem study, which is not
+            reproduced.  The domain is periodic (a 2x2 checkerboard of the states).
 """
 from dataclasses import dataclass, field
 
@@ -100,6 +108,20 @@ def initial_state(w):
         p = np.ones_like(rho)
         E = 0.5 * rho * (Pu ** 2 + Pv ** 2) + p / (gamma - 1.0)
         return np.stack([rho, rho * Pu, rho * Pv, E])
+    if w.name.startswith("riemann2d"):
+        gamma = w.param[0]
+        x = np.arange(w.nx) / w.nx
+        y = np.arange(w.ny) / w.ny
+        right = (x >= 0.5)[None, :]
+        top = (y >= 0.5)[:, None]
+        prim = {(True, True): (1.0, 0.0, 0.0, 1.0), (False, True): (0.6, 0.3, 0.0, 0.5),
+                (False, False): (1.0, 0.3, 0.3, 1.0), (True, False): (0.6, 0.0, 0.3, 0.5)}
+        rho, u, v, p = (np.zeros((w.ny, w.nx)) for _ in range(4))
+        for (r, t), (a, b, c, d) in prim.items():
+            mask = np.logical_and(right == r, top == t)
+            rho[mask], u[mask], v[mask], p[mask] = a, b, c, d
+        E = 0.5 * rho * (u ** 2 + v ** 2) + p / (gamma - 1.0)
+        return np.stack([rho, rho * u, rho * v, E])
     if w.name.startswith("sw2d"):
         Ph = spectral_field_2d(w.nx, w.ny, rng, 4, 1.0)
         Pu = spectral_field_2d(w.nx, w.ny, rng, 4, 1.0)
@@ -124,6 +146,18 @@ def euler2d(n=4096, ny=None, seed=0, nsteps=500, amp=0.05):
 def euler2d_adjoint(n=1024, seed=0, nsteps=2000):
     return Workload("euler2d_adjoint", "D2Q4", "euler", n, n, 3.2, (1.4,), nsteps, seed,
                     extra={"amp": 0.005, "ckpt_every": 50, "target_seed": 1, "fd_seed": 2, "fd_dirs": 32})
+
+
+# schemes of the Sec. 6.3 comparison: (A) standard LB with omega = 1.93, (B) the
+# projected basic brick, (C) the fourth-order scheme with omega = 2 and
+# projections after every brick (Scheme III)
+RIEMANN_SCHEMES = {"A": dict(scheme=5, relax="fixed", omega=1.93),
+                   "B": dict(scheme=6, relax="fixed", omega=2.0),
+                   "C": dict(scheme=3, relax="fixed", omega=2.0)}
+
+
+def riemann2d(n=1024, T=0.25):
+    return Workload("riemann2d", "D2Q4", "euler", n, n, 6.21, (1.4,), 0, 0, relax="fixed", extra={"T": T})
 
 
 def sw2d_instance(i):
