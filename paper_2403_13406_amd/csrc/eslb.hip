@@ -454,7 +454,8 @@ __global__ __launch_bounds__(kDiagThreads) void k_diag(Grid g, Phys P, double* p
 #pragma unroll
       for (int m = 0; m < M; ++m) d[k][m] = f[k][m] - feq[k][m];
     double F = 0.0, dF = 0.0;
-    const bool ok = fsum<S>(c, feq, d, 1.0, F, dF, P);
+    bool unused = false;
+    const bool ok = fsum<S>(c, feq, d, 1.0, F, dF, P, -1.0, unused);
     const double Su = S::macro_entropy(c, P);
     acc[M + 1] += Su;
     if (ok) acc[M] += Su + F; else ++n_out;
