@@ -81,3 +81,55 @@ def test_skipped_confirmation_stays_within_the_stop_rule(frac, seed):
     fsc = np.maximum(np.max(np.abs(feq), axis=(0, 1)), np.max(np.abs(f), axis=(0, 1)))
     effect = np.abs(lp - lam) * dmax / (2 * EPS * fsc)
     assert effect[use].max() <= 1.0, effect[use].max()
+
+
+@pytest.mark.parametrize("D,frac,seed", [(1, 0.9, 21), (1, 0.999, 22), (2, 0.9, 23), (2, 0.999, 24)])
+def test_skipped_confirmation_shallow_water(D, frac, seed):
+    """Shallow water: measure |dh|/h, |e_1|/f_1, |dn|/W at t = -1 against 2^-8 m^2, m = 1 - g h/W_min^2.
+
+    The shallow-water root is itself only determined to about the stop tolerance on both sides (the rounding
+    floor of this comparison is ~1 tolerance for every z), so the bound here is 1.5 tolerances.
+    """
+    from oracle.systems import ShallowWater
+    g, V = 9.81, (4.5 if D == 1 else 8.0)
+    lat = Lattice("D1Q2" if D == 1 else "D2Q4")
+    sysm = ShallowWater(g, D)
+    M = D + 1
+    rng = np.random.default_rng(seed)
+    h = np.exp(rng.uniform(np.log(0.01), np.log(5), 4000))
+    W0 = 2 * lat.w * V
+    lim = frac * W0 - np.sqrt(g * h)
+    keep = lim > 0.002
+    h, lim = h[keep], lim[keep]
+    n = h.size
+    vel = [rng.uniform(-1, 1, n) * lim for _ in range(D)]
+    U0 = np.stack([h] + [h * v for v in vel])
+    feq0 = equilibrium(lat, sysm, V, U0.reshape(M, 1, n)).reshape(lat.q, M, n)
+    rel = 10.0 ** rng.uniform(-6, -1.5, n)
+    f = feq0 + rel * np.abs(feq0) * rng.uniform(-1, 1, feq0.shape)
+    U = f.sum(0)
+    feq = equilibrium(lat, sysm, V, U.reshape(M, 1, n)).reshape(lat.q, M, n)
+    d = f - feq
+    one = np.ones(n)
+    F1, dF1, ok1 = bregman_sum(lat, sysm, V, U, feq, d, one)
+    Fm, dFm, okm = bregman_sum(lat, sysm, V, U, feq, d, -one)
+    lam, fallback = entropic_lambda(lat, sysm, V, U, feq, d)
+    h0 = U[0]
+    v0 = [U[1 + j] / h0 for j in range(D)]
+    Wmin = W0 - np.max(np.abs(np.array(v0)), axis=0)
+    m = 1 - g * h0 / Wmin ** 2
+    zlim = np.where((Wmin > 0) & (m > 0), SKIP * m * m, -1.0)
+    small = np.ones(n, bool)
+    for k in range(lat.q):
+        ax, s = lat.axis[k], lat.sign[k]
+        h1, v1, valid = sysm.population_state(lat, V, k, feq[k] - d[k])
+        Wk = W0 + s * v0[ax]
+        small &= valid & (np.abs(h1 - h0) <= zlim * h0) & (np.abs(d[k][0]) <= zlim * feq[k][0])
+        small &= np.abs(v1[ax] - v0[ax]) <= zlim * Wk
+    use = small & ok1 & okm & ~fallback & (F1 > 0)
+    assert use.sum() > 300 and (~use).sum() > 300
+    lp = hermite_prediction(F1, dF1, Fm, dFm)
+    dmax = np.max(np.abs(d), axis=(0, 1))
+    fsc = np.maximum(np.max(np.abs(feq), axis=(0, 1)), np.max(np.abs(f), axis=(0, 1)))
+    effect = np.abs(lp - lam) * dmax / (2 * EPS * fsc)
+    assert effect[use].max() <= 1.5, effect[use].max()
