@@ -214,19 +214,30 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_stage(Grid gh, double* __res
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   if (x >= gh.nx || y >= gh.ny) return;
+  double u[M], d[Q][M], lam, om;
+  bool grad;
+  unsigned flags = 0;
+  {
+    double h[Q][M];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const long long i = storage_index<D>(gh, k, x, y);
+#pragma unroll
+      for (int m = 0; m < M; ++m) h[k][m] = gh.f[(long long)(k * M + m) * gh.plane + i];
+    }
+    adjoint_root<S>(h, mode, P, flags, u, d, lam, om, grad);
+  }
+  // the cotangent is read only once the forward relaxation is known (and the
+  // storage indices are rebuilt rather than held through the root iteration)
   long long id[Q];
-  double h[Q][M], gb[Q][M];
+  double gb[Q][M];
 #pragma unroll
   for (int k = 0; k < Q; ++k) {
     id[k] = storage_index<D>(gh, k, x, y);
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-      h[k][m] = gh.f[(long long)(k * M + m) * gh.plane + id[k]];
-      gb[k][m] = gbar[(long long)(k * M + m) * gh.plane + id[k]];
-    }
+    for (int m = 0; m < M; ++m) gb[k][m] = gbar[(long long)(k * M + m) * gh.plane + id[k]];
   }
-  unsigned flags = 0;
-  adjoint_node<S>(h, gb, mode, P, flags);
+  adjoint_apply<S>(u, d, lam, om, grad, gb, P);
   bool fin = true;
 #pragma unroll
   for (int k = 0; k < Q; ++k)

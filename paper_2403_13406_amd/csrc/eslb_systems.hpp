@@ -714,7 +714,30 @@ __device__ __forceinline__ void dv_all(const typename S::Node& c, const double (
     double B;
     bool unused;
     (void)S::template bregman<k, true>(c, feq[k], d[k], t, B, dv[k], P, -1.0, unused);
-    dv_all<S, k + 1>(c, feq, d, t, dv, P);
+    // serialise the velocities, as in fsum (interleaved, they spill)
+    double ts = t;
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) asm volatile("" : "+v"(ts) : "v"(dv[k][m]));
+    dv_all<S, k + 1>(c, feq, d, ts, dv, P);
+  }
+}
+
+// gb[k] -= r dv_k(t) for every velocity, dv_k computed one velocity at a time.
+template <class S, int k = 0>
+__device__ __forceinline__ void sub_dv(const typename S::Node& c, const double (&feq)[S::Q][S::M],
+                                       const double (&d)[S::Q][S::M], double t, double r, double (&gb)[S::Q][S::M],
+                                       const Phys& P) {
+  if constexpr (k < S::Q) {
+    double B, dv[S::M];
+    bool unused;
+    (void)S::template bregman<k, true>(c, feq[k], d[k], t, B, dv, P, -1.0, unused);
+    double ts = t;
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) {
+      gb[k][m] -= r * dv[m];
+      asm volatile("" : "+v"(ts) : "v"(gb[k][m]));
+    }
+    sub_dv<S, k + 1>(c, feq, d, ts, r, gb, P);
   }
 }
 
@@ -724,16 +747,21 @@ __device__ __forceinline__ void dv_all(const typename S::Node& c, const double (
 //   c = sum_k (f^eq_k - h_k) . gbar_k,
 //   grad_{h_j} omega = [(1-omega) dv_j(-lambda) + omega sum_k J_k^T dv_k(-lambda) - dv_j(1)] / F'(-lambda),
 // dv_k(t) = v(U_k(t)) - v(u) (implicit function theorem on Sigma(R_omega h) = Sigma(h)).
+// Two phases, so that the cotangent is not held through the root iteration:
+// adjoint_root takes h to (u, d, lambda, omega, grad) -- the forward pass's
+// relaxation, grad = omega depends on h -- and adjoint_apply updates gbar.
 template <class S>
-__device__ inline void adjoint_node(const double (&h)[S::Q][S::M], double (&gb)[S::Q][S::M], int mode,
-                                    const Phys& P, unsigned& flags) {
+__device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
+                                    double (&u)[S::M], double (&d)[S::Q][S::M], double& lam, double& om,
+                                    bool& grad) {
   constexpr int Q = S::Q, M = S::M;
-  double u[M], feq[Q][M], d[Q][M], dmax, fsc;
+  double feq[Q][M], dmax, fsc;
   node_split<S>(h, u, feq, d, dmax, fsc, P);
   typename S::Node c;
   const bool adm = S::prepare(u, c, P);
-  double om = P.omega, lam = P.omega - 1.0;
-  bool grad = false;
+  om = P.omega;
+  lam = P.omega - 1.0;
+  grad = false;
   if (mode == 1) {
     if (!adm) flags |= FLAG_INADMISSIBLE;
     if (dmax == 0.0) {
@@ -749,12 +777,21 @@ __device__ inline void adjoint_node(const double (&h)[S::Q][S::M], double (&gb)[
     }
     om = lam + 1.0;
   }
+}
+
+template <class S>
+__device__ inline void adjoint_apply(const double (&u)[S::M], const double (&d)[S::Q][S::M], double lam, double om,
+                                     bool grad, double (&gb)[S::Q][S::M], const Phys& P) {
+  constexpr int Q = S::Q, M = S::M;
+  typename S::Node c;
+  (void)S::prepare(u, c, P);
+  double feq[Q][M];
+  Eq<S>::equilibrium(u, feq, P);
   double JTg[M];
   eq_jacobian_T<S>(c, gb, JTg, P);
   if (grad) {
-    double dvm[Q][M], dv1[Q][M], JTdv[M];
+    double dvm[Q][M], JTdv[M];
     dv_all<S>(c, feq, d, -lam, dvm, P);
-    dv_all<S>(c, feq, d, 1.0, dv1, P);
     double Fp = 0.0, cc = 0.0;
 #pragma unroll
     for (int k = 0; k < Q; ++k)
@@ -769,8 +806,9 @@ __device__ inline void adjoint_node(const double (&h)[S::Q][S::M], double (&gb)[
     for (int k = 0; k < Q; ++k)
 #pragma unroll
       for (int m = 0; m < M; ++m)
-        gb[k][m] = (1.0 - om) * gb[k][m] + om * JTg[m] +
-                   ((1.0 - om) * dvm[k][m] + om * JTdv[m] - dv1[k][m]) * ratio;
+        gb[k][m] = (1.0 - om) * gb[k][m] + om * JTg[m] + ((1.0 - om) * dvm[k][m] + om * JTdv[m]) * ratio;
+    // the -dv(1) ratio term, one velocity at a time (dvm is dead here)
+    sub_dv<S>(c, feq, d, 1.0, ratio, gb, P);
   } else {
 #pragma unroll
     for (int k = 0; k < Q; ++k)
