@@ -64,7 +64,7 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 // near equilibrium) phi(z) = z^2 g(z) with g(z) = sum_j (-1)^j z^j / (j + 2)
 // replaced by its Chebyshev-economised degree-6 polynomial on [-2^-7, 2^-7]
 // (relative error below 2^-52 in binary64; no cancellation between z and
-// log1p(z)); otherwise z - log1p(z) with the library log1p for both.
+// log1p(z)); otherwise z - log1p(z) with log1p_far for both.
 __device__ __forceinline__ double phi_poly(double z) {
   double g = 0.12501220790442075;
   g = fma(g, z, -0.14286901156622775);
@@ -76,13 +76,47 @@ __device__ __forceinline__ double phi_poly(double z) {
   return (z * z) * g;
 }
 
+// log(1 + z) for z > -1 outside the series range: 1 + z = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),
+// s = (m - 1)/(m + 1), |s| <= 0.1716, summed to s^21 (truncation below 1e-18);
+// ln 2 split so that e ln2_hi is exact; the rounding of 1 + z corrected to first
+// order by c/(1 + z), c = z - ((1 + z) - 1).  Few live values: it sits in the
+// cold branch of every Bregman term, where the library log1p costs the
+// relaxation kernels spilled registers.
+__device__ inline double log1p_far(double z) {
+  const double u = 1.0 + z;
+  const double c = z - (u - 1.0);
+  int e;
+  double m = frexp(u, &e);  // m in [1/2, 1)
+  if (m < 0.70710678118654752440) {
+    m += m;
+    --e;
+  }
+  const double s = (m - 1.0) * rcp(m + 1.0);
+  const double s2 = s * s;
+  double p = 1.0 / 21.0;
+  p = fma(p, s2, 1.0 / 19.0);
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  p = fma(p, s2, 1.0);
+  const double de = (double)e;
+  const double rest = fma(de, 0x1.a39ef35793c76p-33, fma(2.0 * s, p, c * rcp(u)));
+  return fma(de, 0x1.62e42fee00000p-1, rest);
+}
+
 __device__ __forceinline__ void phi_pair(double za, double zb, double& pa, double& pb) {
   if ((fabs(za) < 0.0078125) & (fabs(zb) < 0.0078125)) {
     pa = phi_poly(za);
     pb = phi_poly(zb);
   } else {
-    pa = za - log1p(za);
-    pb = zb - log1p(zb);
+    pa = za - log1p_far(za);
+    pb = zb - log1p_far(zb);
   }
 }
 
@@ -184,6 +218,83 @@ template <int D> struct Burgers {
 // dn = 0 follows the branch with W'^2 > g h' (the physical one).  Then
 //   du_t = (e_t - u_t e_1) / x_1,  dh = 2V (e_1 W - sigma f^eq_1 dn) / (W W'),
 //   B = [g W dh^2 + 2 sigma g h' dh dn + h' W' |du|^2] / (4V).
+// Admissibility of a root dn of the shallow-water population-state cubic:
+// W' = W + sigma dn > 0, h' = h + dh > 0, W'^2 > g h', x_1 > 0.
+__device__ inline bool sw_root_admissible(double dn, double W, double s, double e1, double f1, double x1, double h,
+                                          double g, double V) {
+  const double Wp = W + s * dn;
+  const double hp = h + 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
+  return (x1 > 0.0) & (Wp > 0.0) & (hp > 0.0) & (Wp * Wp > g * hp);
+}
+
+// The branch rule on the population-state cubic P3 x^3 + P2 x^2 + P1 x + P0
+// (P3 = -x_1 W^2 < 0), for the rare nodes where Newton from the cell state is not
+// trustworthy: the extreme admissible real root -- largest for sigma = +1,
+// smallest for sigma = -1 -- or NaN when there is none (the population state is
+// then outside the domain).  With one real root (negative discriminant) it is
+// bracketed by the Cauchy bound U = 1 + max |P_i / P3| (P(-U) > 0 > P(U)) and
+// found by Newton safeguarded with bisection; with three, Newton from +-U runs
+// monotonically onto the extreme one, and if that one is not admissible the
+// other two come from the deflated quadratic.  No transcendental functions.
+__device__ inline double sw_branch_root(double P0, double P1, double P2, double P3, double W, double s, double e1,
+                                        double f1, double x1, double h, double g, double V) {
+  const double i3 = rcp(P3);
+  const double U = 1.0 + fmax(fabs(P2 * i3), fmax(fabs(P1 * i3), fabs(P0 * i3)));
+  const double disc = 18.0 * P3 * P2 * P1 * P0 - 4.0 * P2 * P2 * P2 * P0 + P2 * P2 * P1 * P1 -
+                      4.0 * P3 * P1 * P1 * P1 - 27.0 * P3 * P3 * P0 * P0;
+  if (disc < 0.0) {
+    double lo = -U, hi = U, x = 0.0;
+    bool conv = false;
+#pragma unroll 1
+    for (int it = 0; it < 200; ++it) {
+      const double Pv = P0 + x * (P1 + x * (P2 + x * P3));
+      if (Pv > 0.0) {
+        lo = x;
+      } else {
+        hi = x;
+      }
+      const double dP = P1 + x * (2.0 * P2 + 3.0 * P3 * x);
+      double xn = x - Pv / dP;
+      if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+      const double st = xn - x;
+      x = xn;
+      if (!(fabs(st) > 0x1p-40 * fabs(x)) || !((hi - lo) > 0x1p-40 * fabs(x))) {
+        conv = true;
+        break;
+      }
+    }
+    return (conv && sw_root_admissible(x, W, s, e1, f1, x1, h, g, V)) ? x : NAN;
+  }
+  double x = s * U;
+#pragma unroll 1
+  for (int it = 0; it < 200; ++it) {
+    const double st = (P0 + x * (P1 + x * (P2 + x * P3))) / (P1 + x * (2.0 * P2 + 3.0 * P3 * x));
+    x -= st;
+    if (!(fabs(st) > 0x1p-40 * fabs(x))) break;
+  }
+  if (sw_root_admissible(x, W, s, e1, f1, x1, h, g, V)) return x;
+  const double B1 = P2 + P3 * x, C1 = P1 + B1 * x;
+  const double dq = B1 * B1 - 4.0 * P3 * C1;
+  double best = NAN;
+  if (dq >= 0.0) {
+    const double qq = -0.5 * (B1 + copysign(sqrt(dq), B1));
+    const double cand[2] = {qq * i3, C1 / qq};
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double y = cand[i];
+      if (isfinite(y) && sw_root_admissible(y, W, s, e1, f1, x1, h, g, V) &&
+          (isnan(best) || (s > 0.0 ? y > best : y < best)))
+        best = y;
+    }
+  }
+  if (isfinite(best)) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      best -= (P0 + best * (P1 + best * (P2 + best * P3))) / (P1 + best * (2.0 * P2 + 3.0 * P3 * best));
+  }
+  return best;
+}
+
 template <int D> struct ShallowWater {
   static constexpr int M = D + 1, Q = Lat<D>::Q;
   struct Node { double h, vel[D]; };
@@ -259,10 +370,14 @@ template <int D> struct ShallowWater {
     const double P2 = gV * a * a + W2 * (gn - 2.0 * s * x1 * W);
     const double P3 = -x1 * W2;
     // start from the second-order series reversion of the root about dn = 0,
-    // -P0/P1 - P2 P0^2/P1^3 (error O(dn^3)), then Newton
+    // -P0/P1 - P2 P0^2/P1^3 (error O(dn^3)), while its correction is a small change
+    // of the first Newton iterate from 0 (|P2 d0 / P1| <= 1/4); otherwise from that
+    // iterate itself.  Then Newton.
     const double rP1 = rcp(P1);
     const double d0 = -P0 * rP1;
-    double dn = d0 * (1.0 - P2 * d0 * rP1);
+    const double q = P2 * d0 * rP1;
+    double dn = fabs(q) <= 0.25 ? d0 * (1.0 - q) : d0;
+    bool conv = false;
 #pragma unroll 1
     for (int it = 0; it < 12; ++it) {
       const double Pv = P0 + dn * (P1 + dn * (P2 + dn * P3));
@@ -270,11 +385,23 @@ template <int D> struct ShallowWater {
       const double st = Pv * rcp(dP);
       dn -= st;
       // quadratic convergence: once a step is below 2^-40 |dn| the error left is ~2^-80 |dn|
-      if (!(fabs(st) > 0x1p-40 * fabs(dn))) break;
+      if (!(fabs(st) > 0x1p-40 * fabs(dn))) {
+        conv = true;
+        break;
+      }
     }
-    const double Wp = W + s * dn;
-    const double dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
-    const double hp = c.h + dh;
+    // Far from the cell state (no convergence, |dn| > W/20, or a root outside the
+    // admissible set) Newton may have run to another root of the cubic (near the
+    // sonic point P1 -> 0): take the branch rule itself (sw_branch_root).
+    double Wp = W + s * dn;
+    double dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
+    double hp = c.h + dh;
+    if (!conv || fabs(dn) > 0.05 * W || !((x1 > 0.0) & (Wp > 0.0) & (hp > 0.0) & (Wp * Wp > g * hp))) {
+      dn = sw_branch_root(P0, P1, P2, P3, W, s, e1, f1, x1, c.h, g, V);
+      Wp = W + s * dn;
+      dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
+      hp = c.h + dh;
+    }
     small = (fabs(dh) <= zlim * c.h) & (fabs(e1) <= zlim * f1) & (fabs(dn) <= zlim * W);
     double du2 = dn * dn;
     double kin = dn * (2.0 * un + dn);
