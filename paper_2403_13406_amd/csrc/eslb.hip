@@ -97,9 +97,11 @@ __device__ __forceinline__ void record_omega(DevStats* st, bool act, double om) 
 // One relaxation pass (the shift that precedes it is in g.sh).  Off32: planes
 // of at most kPlane32 nodes (32-bit byte offsets); otherwise 64-bit indices.
 template <class S, int D, bool Off32>
-// two waves per SIMD: fewer registers than the unconstrained build (one wave) but
-// no real spilling; measured 1.40x faster on the Euler stage
-__global__ __launch_bounds__(256, 2) void k_stage(Grid g, Planes pl, Phys P, int mode, int track, DevStats* st) {
+// S::kStageBlocks blocks of 256 threads per CU: two waves per SIMD for the heavy
+// systems (fewer registers than the unconstrained build's one wave, no spilling;
+// measured 1.40x faster on the Euler stage), four for 1D shallow water
+__global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes pl, Phys P, int mode, int track,
+                                                               DevStats* st) {
   constexpr int Q = S::Q, M = S::M;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;

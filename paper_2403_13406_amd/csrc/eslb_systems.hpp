@@ -140,6 +140,7 @@ template <> struct Lat<2> {
 // phi^j = a_j u, S = u^2/2; s_k(x) = x^2 / (2 w_k), w_k = w + sigma a_n / (2V)
 // (Example "Linear transport equation", Sec. 1.2.1 and 1.2.2).
 template <int D> struct Advection {
+  static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
   __device__ static double skip_limit(const Node&, const Phys&) { return -1.0; }  // no skip measure
@@ -173,6 +174,7 @@ template <int D> struct Advection {
 // Increment equation of the population state: (beta/4V) dU^2 + c1 dU - e = 0,
 // c1 = w + beta u / (2V); B = dU^2 (w/2 + beta (3u + 2 dU) / (12V)).
 template <int D> struct Burgers {
+  static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
   __device__ static double skip_limit(const Node&, const Phys&) { return -1.0; }  // no skip measure
@@ -296,6 +298,7 @@ __device__ inline double sw_branch_root(double P0, double P1, double P2, double 
 }
 
 template <int D> struct ShallowWater {
+  static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int M = D + 1, Q = Lat<D>::Q;
   struct Node { double h, vel[D]; };
   // skip measure of the predictor (see Euler2): |dh|/h, |e_1|/f_1 and
@@ -449,6 +452,7 @@ template <int D> struct ShallowWater {
 
 struct Euler2 {
   static constexpr int D = 2, M = 4, Q = 4;
+  static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   struct Node { double rho, vel[2], p, E, irho, ip; };
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
     const double rho = u[0], ir = rcp(rho);

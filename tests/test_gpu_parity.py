@@ -126,6 +126,28 @@ def test_one_pass_far_from_equilibrium(system, rel):
     assert max(err) <= PARITY_RTOL, err
 
 
+@pytest.mark.parametrize("system,param,V,rel", [("shallow_water", (9.81,), 4.5, 0.05), ("shallow_water", (9.81,), 4.5, 0.2),
+                                                ("burgers", (1.0,), 2.0, 0.05), ("burgers", (1.0,), 2.0, 0.3)])
+def test_one_pass_far_from_equilibrium_1d(system, param, V, rel):
+    """D1Q2 entropic relaxation of stage inputs with relative offsets from f^eq up to rel."""
+    lat, sys = oracle_system("D1Q2", system, param)
+    n = 3001
+    rng = np.random.default_rng(32)
+    if system == "shallow_water":
+        u = np.stack([1.0 + 0.1 * rng.standard_normal(n), 0.1 * rng.standard_normal(n)])[:, None, :]
+    else:
+        u = (0.4 + 0.1 * rng.standard_normal(n))[None, None, :]
+    feq = equilibrium(lat, sys, V, u)
+    f0 = feq + rel * np.abs(feq) * rng.uniform(-1.0, 1.0, feq.shape)
+    from paper_2403_13406_amd import Solver
+    s = Solver("D1Q2", system, n, 1, V=V, relax="entropic", param=param)
+    fg = to_gpu(f0)
+    s.relax(fg)
+    s.sync()
+    err = componentwise_error(to_host(fg), relax_entropic(lat, sys, V, f0))
+    assert max(err) <= PARITY_RTOL, err
+
+
 # ------------------------------------------------------------------ composed steps
 
 @pytest.mark.parametrize("name,nsteps", [("burgers1d", 17), ("sw1d", 1), ("sw1d", 10), ("euler2d", 1), ("euler2d", 10),
