@@ -186,20 +186,49 @@ int eslb_moments_adjoint(eslb_ctx* ctx, const double* ubar_dev, double* fbar_dev
 /* Adjoint of eslb_init_equilibrium: ubar = sum_k (d f_k^eq / du)(u)^T fbar_k.
  * u_dev, ubar_dev: M planes; fbar_dev: q*M planes, logical layout.  Asynchronous. */
 int eslb_init_adjoint(eslb_ctx* ctx, const double* u_dev, const double* fbar_dev, double* ubar_dev);
-/* Device bytes eslb_adjoint needs for (nsteps, ckpt_every):
- * (ceil(nsteps/ckpt_every) + ckpt_every + passes_per_step + 2) states. */
+/* Device bytes eslb_adjoint needs for (nsteps, ckpt_every), with L =
+ * min(ckpt_every, nsteps) steps per segment and P = passes per step:
+ * (ceil(nsteps/ckpt_every) + 2 + L + P) states plus P planes of nx*ny doubles
+ * (each pass's lambda). */
 int eslb_adjoint_workspace_bytes(const eslb_ctx* ctx, int64_t nsteps, int64_t ckpt_every, size_t* bytes);
+/* Device bytes with which eslb_adjoint records a whole segment at once:
+ * (ceil(nsteps/ckpt_every) + 2 + L P) states plus L P lambda planes (L, P as
+ * above).  Given at least this much workspace, eslb_adjoint recomputes every
+ * step once instead of twice; the result is the same to the bit. */
+int eslb_adjoint_tape_bytes(const eslb_ctx* ctx, int64_t nsteps, int64_t ckpt_every, size_t* bytes);
 /* Cotangent of the initial distributions through nsteps composed steps.
  * f0_dev: the forward initial state in storage layout with the context's current
  * offsets (read only).  fbar_dev: on entry the cotangent of the state after
  * nsteps steps, on return the cotangent of f0; both in logical layout (offsets
  * applied, as eslb_gather returns).  work_dev: caller-owned device workspace of at
- * least eslb_adjoint_workspace_bytes bytes.  Checkpoints every ckpt_every steps,
- * recomputes each segment's step states and each step's stage inputs, then runs
- * the adjoint passes in reverse.  The context's offsets are unchanged on return.
+ * least eslb_adjoint_workspace_bytes bytes.  Checkpoints every ckpt_every steps;
+ * per segment, in reverse, every pass of every step is recomputed with a record
+ * of its input and its lambda, and the adjoint passes run in reverse from those
+ * records (no root search in the adjoint).  With eslb_adjoint_tape_bytes of
+ * workspace a segment is recomputed once, recording every step; with less, the
+ * segment's step states are recomputed first and each step is run again,
+ * recording, just before its adjoint passes.  The context's offsets are
+ * unchanged on return.
  * Asynchronous. */
 int eslb_adjoint(eslb_ctx* ctx, const double* f0_dev, int64_t nsteps, int64_t ckpt_every, double* fbar_dev,
                  void* work_dev, size_t work_bytes);
+/* Device bytes of the checkpoints of (nsteps, ckpt_every): ceil(nsteps/ckpt_every)
+ * states. */
+int eslb_checkpoint_bytes(const eslb_ctx* ctx, int64_t nsteps, int64_t ckpt_every, size_t* bytes);
+/* eslb_step(f_dev, nsteps) that also copies the state at steps 0, ckpt_every,
+ * 2 ckpt_every, ... (storage layout, as it stands at that step) into ckpt_dev, a
+ * caller-owned buffer of at least eslb_checkpoint_bytes bytes; a forward run that
+ * keeps what eslb_adjoint_checkpointed needs.  Offsets advance as in eslb_step.
+ * Asynchronous. */
+int eslb_step_checkpointed(eslb_ctx* ctx, double* f_dev, int64_t nsteps, int64_t ckpt_every, double* ckpt_dev);
+/* eslb_adjoint from the checkpoints of an eslb_step_checkpointed run instead of
+ * its own forward sweep: the context's offsets must be those the run started
+ * from (they are unchanged on return); ckpt_dev is read only; fbar_dev as in
+ * eslb_adjoint.  work_dev: at least eslb_adjoint_workspace_bytes -
+ * eslb_checkpoint_bytes bytes (taped with eslb_adjoint_tape_bytes -
+ * eslb_checkpoint_bytes).  Same bits as eslb_adjoint.  Asynchronous. */
+int eslb_adjoint_checkpointed(eslb_ctx* ctx, const double* ckpt_dev, int64_t nsteps, int64_t ckpt_every,
+                              double* fbar_dev, void* work_dev, size_t work_bytes);
 
 /* ---------------------------------------------------------------- batched ensembles
  * Many independent problems of one kind (same lattice, system, relax mode, scheme

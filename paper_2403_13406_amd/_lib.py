@@ -54,6 +54,11 @@ _SIGNATURES = {
     "eslb_moments_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "eslb_init_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "eslb_adjoint_workspace_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
+    "eslb_adjoint_tape_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
+    "eslb_checkpoint_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
+    "eslb_step_checkpointed": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p]),
+    "eslb_adjoint_checkpointed": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_void_p,
+                                            ctypes.c_size_t]),
     "eslb_adjoint": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_void_p, ctypes.c_size_t]),
     "eslb_batch_create": (c_int32, [P(Problem), c_int32, c_void_p, P(c_void_p)]),
     "eslb_batch_destroy": (None, [c_void_p]),

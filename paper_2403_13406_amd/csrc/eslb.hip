@@ -96,12 +96,16 @@ __device__ __forceinline__ void record_omega(DevStats* st, bool act, double om) 
 
 // One relaxation pass (the shift that precedes it is in g.sh).  Off32: planes
 // of at most kPlane32 nodes (32-bit byte offsets); otherwise 64-bit indices.
-template <class S, int D, bool Off32>
+// Rec (the adjoint's recomputation): the pass input is also written to the
+// planes rec (same storage layout and offsets) and lambda to lamr (logical node
+// order; NaN where the root search fell back), so the adjoint pass needs no
+// copy of its input and no root search.
+template <class S, int D, bool Off32, bool Rec = false>
 // S::kStageBlocks blocks of 256 threads per CU: two waves per SIMD for the heavy
 // systems (fewer registers than the unconstrained build's one wave, no spilling;
 // measured 1.40x faster on the Euler stage), four for 1D shallow water
 __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes pl, Phys P, int mode, int track,
-                                                               DevStats* st) {
+                                                               DevStats* st, Planes rec, double* lamr) {
   constexpr int Q = S::Q, M = S::M;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -119,7 +123,17 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
 #pragma unroll
         for (int m = 0; m < M; ++m) f[k][m] = plane_at(pl.p[k * M + m], off[k]);
       }
-      om = relax_node<S>(f, mode, P, flags);
+      if constexpr (Rec) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) plane_at(rec.p[k * M + m], off[k]) = f[k][m];
+        double lam;
+        om = relax_node<S>(f, mode, P, flags, lam);
+        if (mode == 1) lamr[(unsigned)y * (unsigned)g.nx + (unsigned)x] = lam;
+      } else {
+        om = relax_node<S>(f, mode, P, flags);
+      }
 #pragma unroll
       for (int k = 0; k < Q; ++k)
 #pragma unroll
@@ -135,7 +149,17 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
 #pragma unroll
         for (int m = 0; m < M; ++m) f[k][m] = g.f[(long long)(k * M + m) * g.plane + id[k]];
       }
-      om = relax_node<S>(f, mode, P, flags);
+      if constexpr (Rec) {
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+#pragma unroll
+          for (int m = 0; m < M; ++m) rec.p[k * M + m][id[k]] = f[k][m];
+        double lam;
+        om = relax_node<S>(f, mode, P, flags, lam);
+        if (mode == 1) lamr[(long long)y * g.nx + x] = lam;
+      } else {
+        om = relax_node<S>(f, mode, P, flags);
+      }
 #pragma unroll
       for (int k = 0; k < Q; ++k)
 #pragma unroll
@@ -209,9 +233,10 @@ __global__ __launch_bounds__(256) void k_gather(Grid g, double* __restrict__ out
 
 // Adjoint of one relaxation pass: h = stage input (storage, offsets in gh.sh),
 // gbar = cotangent of the stage output in the same storage; overwritten with hbar.
-template <class S, int D>
+// Taped: lamr holds the forward pass's lambda per node (k_stage with Rec).
+template <class S, int D, bool Taped = false>
 __global__ __launch_bounds__(256, 2) void k_adjoint_stage(Grid gh, double* __restrict__ gbar, Phys P, int mode,
-                                                        DevStats* st) {
+                                                        DevStats* st, const double* __restrict__ lamr) {
   constexpr int Q = S::Q, M = S::M;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
@@ -227,7 +252,12 @@ __global__ __launch_bounds__(256, 2) void k_adjoint_stage(Grid gh, double* __res
 #pragma unroll
       for (int m = 0; m < M; ++m) h[k][m] = gh.f[(long long)(k * M + m) * gh.plane + i];
     }
-    adjoint_root<S>(h, mode, P, flags, u, d, lam, om, grad);
+    if constexpr (Taped) {
+      const double lr = (mode == 1) ? lamr[(long long)y * gh.nx + x] : 0.0;
+      adjoint_taped<S>(h, mode, lr, P, u, d, lam, om, grad);
+    } else {
+      adjoint_root<S>(h, mode, P, flags, u, d, lam, om, grad);
+    }
   }
   // the cotangent is read only once the forward relaxation is known (and the
   // storage indices are rebuilt rather than held through the root iteration)
@@ -580,25 +610,40 @@ void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
 
 #define ESLB_DISPATCH(KIND, CALL) ESLB_DISPATCH_KIND(KIND, CALL)
 
-int launch_stage(eslb_ctx* c, double* f, int mode) {
+// rec (optional): q*M planes that receive the pass input, and lamr (optional
+// with rec; needed for mode 1) one plane for lambda; see k_stage.
+int launch_stage(eslb_ctx* c, double* f, int mode, double* rec, double* lamr) {
   const Grid g = make_grid(c, f);
   dim3 grid, block;
   launch_shape(c, grid, block);
   const int track = (mode == 1) ? c->track : 0;
   Phys P = c->phys;
-  Planes pl{};
+  Planes pl{}, rp{};
   for (int i = 0; i < c->q * c->M; ++i) pl.p[i] = f + (long long)i * g.plane;
-  if (g.plane <= kPlane32) {
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st)
+  if (rec)
+    for (int i = 0; i < c->q * c->M; ++i) rp.p[i] = rec + (long long)i * g.plane;
+  const bool o32 = g.plane <= kPlane32;
+  if (o32 && !rec) {
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true, false>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
+    ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  } else if (!rec) {
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false, false>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
+    ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  } else if (o32) {
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true, true>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
     ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
   } else {
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st)
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false, true>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
     ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
   }
   return hip_check(c, hipGetLastError(), "stage kernel launch");
 }
+
+int launch_stage(eslb_ctx* c, double* f, int mode) { return launch_stage(c, f, mode, nullptr, nullptr); }
 
 static int kind_of(const eslb_problem& p, int* d, int* q, int* M) {
   if (p.lattice == ESLB_D1Q2) {
@@ -727,7 +772,8 @@ int run_pass(eslb_ctx* c, double* f, int shift, int op) {
 }
 
 
-int launch_adjoint_stage(eslb_ctx* c, const double* h, double* gbar, int op) {
+// lamr (optional): the forward pass's lambda plane (launch_stage with rec).
+int launch_adjoint_stage(eslb_ctx* c, const double* h, double* gbar, int op, const double* lamr = nullptr) {
   const Grid g = make_grid(c, const_cast<double*>(h));
   dim3 grid, block;
   launch_shape(c, grid, block);
@@ -737,9 +783,15 @@ int launch_adjoint_stage(eslb_ctx* c, const double* h, double* gbar, int op) {
     P.omega = 1.0;
     mode = 0;
   }
-#define CALL(S, D) hipLaunchKernelGGL((k_adjoint_stage<S, D>), grid, block, 0, c->stream, g, gbar, P, mode, c->st)
-  ESLB_DISPATCH(c->kind, CALL)
+  if (lamr && mode == 1) {
+#define CALL(S, D) hipLaunchKernelGGL((k_adjoint_stage<S, D, true>), grid, block, 0, c->stream, g, gbar, P, mode, c->st, lamr)
+    ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
+  } else {
+#define CALL(S, D) hipLaunchKernelGGL((k_adjoint_stage<S, D, false>), grid, block, 0, c->stream, g, gbar, P, mode, c->st, lamr)
+    ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  }
   return hip_check(c, hipGetLastError(), "adjoint stage launch");
 }
 
@@ -765,9 +817,116 @@ long long net_shift(const eslb_ctx* c) {
   return s;
 }
 
-size_t adjoint_states(const eslb_ctx* c, int64_t nsteps, int64_t ck) {
+// Workspace of the reverse sweep (beyond the checkpoints): running state,
+// cotangent, and pass records.  Per-step recomputation: one segment's step
+// states, one step's stage inputs and lambda planes.  Taped: the stage input and
+// lambda plane of every pass of one segment.
+size_t sweep_bytes(const eslb_ctx* c, int64_t nsteps, int64_t ck, bool taped) {
+  const int64_t lseg = std::min<int64_t>(ck, nsteps);
+  size_t sb = 0;
+  eslb_state_bytes(c, &sb);
+  const size_t plane_bytes = (size_t)c->pb.nx * c->pb.ny * sizeof(double), np = c->passes.size();
+  const size_t nrec = taped ? (size_t)lseg * np : np;
+  return (2 + (taped ? 0 : (size_t)lseg) + nrec) * sb + nrec * plane_bytes;
+}
+
+size_t checkpoint_bytes(const eslb_ctx* c, int64_t nsteps, int64_t ck) {
+  size_t sb = 0;
+  eslb_state_bytes(c, &sb);
+  return (size_t)((nsteps + ck - 1) / ck) * sb;
+}
+
+// Reverse sweep of eslb_adjoint from the checkpoints ckp (states at steps 0, ck,
+// 2ck, ... in storage layout); the context's offsets are those of step 0.
+int adjoint_sweep(eslb_ctx* c, const double* ckp, int64_t nsteps, int64_t ck, double* fbar, double* wk,
+                  bool taped) {
+  size_t sb = 0;
+  eslb_state_bytes(c, &sb);
+  const size_t sd = sb / sizeof(double);
+  const size_t plane = (size_t)c->pb.nx * c->pb.ny;
   const int64_t nseg = (nsteps + ck - 1) / ck;
-  return (size_t)nseg + (size_t)ck + c->passes.size() + 2;
+  const int64_t lseg = std::min<int64_t>(ck, nsteps);  // steps per segment
+  const int npass = (int)c->passes.size();
+  double* run = wk;        // running state
+  double* cot = run + sd;  // cotangent in storage layout
+  double* seg = cot + sd;  // recomputation: lseg step states of one segment
+  // pass records: stage inputs and lambda planes, of one step (recomputation)
+  // or of every step of a segment (taped)
+  const size_t nrec = taped ? (size_t)lseg * npass : (size_t)npass;
+  double* stin = taped ? seg : seg + (size_t)lseg * sd;
+  double* lamp = stin + nrec * sd;
+  long long o0[4];
+  for (int k = 0; k < 4; ++k) o0[k] = c->off[k];
+  const long long net = net_shift(c);
+  long long all_shifts = 0;
+  for (int p = 0; p < npass; ++p) all_shifts += c->passes[p].shift;
+  auto set_step = [&](int64_t s) {
+    for (int k = 0; k < c->q; ++k) c->off[k] = o0[k] + s * net;
+  };
+  auto copy = [&](double* dst, const double* src) {
+    return hip_check(c, hipMemcpyAsync(dst, src, sb, hipMemcpyDeviceToDevice, c->stream), "device copy");
+  };
+  // the passes of step s on the state f, each recording its input (rec + p sd)
+  // and lambda (lam + p plane)
+  auto record_step = [&](int64_t s, double* f, double* rec, double* lam) {
+    set_step(s);
+    int rc = ESLB_OK;
+    for (int p = 0; p < npass && rc == ESLB_OK; ++p) {
+      add_offsets(c, c->passes[p].shift);
+      double* r = rec + (size_t)p * sd;
+      double* l = lam + (size_t)p * plane;
+      if (c->passes[p].op == PASS_PROJECT) {
+        const double keep = c->phys.omega;
+        c->phys.omega = 1.0;
+        rc = launch_stage(c, f, 0, r, l);
+        c->phys.omega = keep;
+      } else {
+        rc = launch_stage(c, f, c->pb.relax, r, l);
+      }
+    }
+    return rc;
+  };
+  // the adjoint passes of step s in reverse, from its records
+  auto adjoint_step = [&](int64_t s, double* rec, double* lam) {
+    set_step(s);
+    add_offsets(c, all_shifts);
+    int rc = ESLB_OK;
+    for (int p = npass - 1; p >= 0 && rc == ESLB_OK; --p) {
+      rc = launch_adjoint_stage(c, rec + (size_t)p * sd, cot, c->passes[p].op, lam + (size_t)p * plane);
+      add_offsets(c, -c->passes[p].shift);
+    }
+    return rc;
+  };
+  // terminal cotangent into storage layout
+  set_step(nsteps);
+  int rc = launch_layout(c, cot, fbar, true);
+  for (int64_t i = nseg - 1; i >= 0 && rc == ESLB_OK; --i) {
+    const int64_t s0 = i * ck, s1 = std::min<int64_t>(nsteps, s0 + ck);
+    if (taped) {
+      rc = copy(run, ckp + (size_t)i * sd);
+      for (int64_t s = s0; s < s1 && rc == ESLB_OK; ++s)
+        rc = record_step(s, run, stin + (size_t)(s - s0) * npass * sd, lamp + (size_t)(s - s0) * npass * plane);
+      for (int64_t s = s1 - 1; s >= s0 && rc == ESLB_OK; --s)
+        rc = adjoint_step(s, stin + (size_t)(s - s0) * npass * sd, lamp + (size_t)(s - s0) * npass * plane);
+    } else {
+      set_step(s0);
+      rc = copy(seg, ckp + (size_t)i * sd);
+      for (int64_t j = 1; j < s1 - s0 && rc == ESLB_OK; ++j) {
+        rc = copy(seg + (size_t)j * sd, seg + (size_t)(j - 1) * sd);
+        if (rc == ESLB_OK) rc = eslb_step(c, seg + (size_t)j * sd, 1);
+      }
+      for (int64_t s = s1 - 1; s >= s0 && rc == ESLB_OK; --s) {
+        rc = copy(run, seg + (size_t)(s - s0) * sd);
+        if (rc == ESLB_OK) rc = record_step(s, run, stin, lamp);
+        if (rc == ESLB_OK) rc = adjoint_step(s, stin, lamp);
+      }
+    }
+  }
+  // cotangent of the initial state back to logical layout
+  set_step(0);
+  if (rc == ESLB_OK) rc = launch_layout(c, cot, fbar, false);
+  for (int k = 0; k < 4; ++k) c->off[k] = o0[k];
+  return rc;
 }
 
 // Whole run in LDS (see k_run_lds); all velocities share one offset history here.
@@ -1088,88 +1247,69 @@ int eslb_init_adjoint(eslb_ctx* c, const double* u, const double* fbar, double* 
 
 int eslb_adjoint_workspace_bytes(const eslb_ctx* c, int64_t nsteps, int64_t ckpt_every, size_t* bytes) {
   if (!c || !bytes || nsteps < 0 || ckpt_every < 1) return ESLB_ERR_INVALID_ARG;
+  *bytes = checkpoint_bytes(c, nsteps, ckpt_every) + sweep_bytes(c, nsteps, ckpt_every, false);
+  return ESLB_OK;
+}
+
+int eslb_adjoint_tape_bytes(const eslb_ctx* c, int64_t nsteps, int64_t ckpt_every, size_t* bytes) {
+  if (!c || !bytes || nsteps < 0 || ckpt_every < 1) return ESLB_ERR_INVALID_ARG;
+  *bytes = checkpoint_bytes(c, nsteps, ckpt_every) + sweep_bytes(c, nsteps, ckpt_every, true);
+  return ESLB_OK;
+}
+
+int eslb_checkpoint_bytes(const eslb_ctx* c, int64_t nsteps, int64_t ckpt_every, size_t* bytes) {
+  if (!c || !bytes || nsteps < 0 || ckpt_every < 1) return ESLB_ERR_INVALID_ARG;
+  *bytes = checkpoint_bytes(c, nsteps, ckpt_every);
+  return ESLB_OK;
+}
+
+int eslb_step_checkpointed(eslb_ctx* c, double* f, int64_t nsteps, int64_t ck, double* ckpt) {
+  if (!c || !f || !ckpt) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  if (nsteps < 0 || ck < 1) return set_err(c, ESLB_ERR_INVALID_ARG, "nsteps must be >= 0 and ckpt_every >= 1");
   size_t sb = 0;
   eslb_state_bytes(c, &sb);
-  *bytes = adjoint_states(c, nsteps, ckpt_every) * sb;
-  return ESLB_OK;
+  int rc = ESLB_OK;
+  for (int64_t s = 0; s < nsteps && rc == ESLB_OK; s += ck) {
+    rc = hip_check(c, hipMemcpyAsync(ckpt + (size_t)(s / ck) * (sb / sizeof(double)), f, sb,
+                                     hipMemcpyDeviceToDevice, c->stream), "device copy");
+    if (rc == ESLB_OK) rc = eslb_step(c, f, std::min<int64_t>(ck, nsteps - s));
+  }
+  return rc;
+}
+
+int eslb_adjoint_checkpointed(eslb_ctx* c, const double* ckpt, int64_t nsteps, int64_t ck, double* fbar,
+                              void* work, size_t work_bytes) {
+  if (!c || !ckpt || !fbar || !work) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  if (nsteps < 0 || ck < 1) return set_err(c, ESLB_ERR_INVALID_ARG, "nsteps must be >= 0 and ckpt_every >= 1");
+  if (work_bytes < sweep_bytes(c, nsteps, ck, false))
+    return set_err(c, ESLB_ERR_INVALID_ARG, "adjoint workspace too small");
+  const bool taped = work_bytes >= sweep_bytes(c, nsteps, ck, true);
+  return adjoint_sweep(c, ckpt, nsteps, ck, fbar, (double*)work, taped);
 }
 
 int eslb_adjoint(eslb_ctx* c, const double* f0, int64_t nsteps, int64_t ck, double* fbar, void* work,
                  size_t work_bytes) {
   if (!c || !f0 || !fbar || !work) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
   if (nsteps < 0 || ck < 1) return set_err(c, ESLB_ERR_INVALID_ARG, "nsteps must be >= 0 and ckpt_every >= 1");
-  size_t need = 0;
-  eslb_adjoint_workspace_bytes(c, nsteps, ck, &need);
-  if (work_bytes < need) return set_err(c, ESLB_ERR_INVALID_ARG, "adjoint workspace too small");
+  const size_t cb = checkpoint_bytes(c, nsteps, ck);
+  if (work_bytes < cb + sweep_bytes(c, nsteps, ck, false))
+    return set_err(c, ESLB_ERR_INVALID_ARG, "adjoint workspace too small");
+  // with room for a whole segment's pass records, the segment is recomputed
+  // once, recording as it goes; otherwise its step states are recomputed and
+  // each step is run once more, recording, just before its adjoint passes
+  const bool taped = work_bytes >= cb + sweep_bytes(c, nsteps, ck, true);
+  double* ckp = (double*)work;
+  double* wk = ckp + cb / sizeof(double);
   size_t sb = 0;
   eslb_state_bytes(c, &sb);
-  const size_t sd = sb / sizeof(double);
-  const int64_t nseg = (nsteps + ck - 1) / ck;
-  const int npass = (int)c->passes.size();
-  double* base = (double*)work;
-  double* ckp = base;                   // nseg checkpoints (state at steps 0, ck, 2ck, ...)
-  double* seg = ckp + (size_t)nseg * sd; // ck states of one segment
-  double* stin = seg + (size_t)ck * sd;  // npass stage inputs of one step
-  double* run = stin + (size_t)npass * sd;
-  double* cot = run + sd;               // cotangent in storage layout
   long long o0[4];
   for (int k = 0; k < 4; ++k) o0[k] = c->off[k];
-  const long long net = net_shift(c);
-  auto set_step = [&](int64_t s) {
-    for (int k = 0; k < c->q; ++k) c->off[k] = o0[k] + s * net;
-  };
-  auto copy = [&](double* dst, const double* src) {
-    return hip_check(c, hipMemcpyAsync(dst, src, sb, hipMemcpyDeviceToDevice, c->stream), "device copy");
-  };
-  int rc = ESLB_OK;
-  // 1) forward sweep, keeping a checkpoint every ck steps
-  rc = copy(run, f0);
-  for (int64_t s = 0; s < nsteps && rc == ESLB_OK; ++s) {
-    if (s % ck == 0) rc = copy(ckp + (size_t)(s / ck) * sd, run);
-    if (rc == ESLB_OK) rc = eslb_step(c, run, 1);
-  }
-  // 2) terminal cotangent into storage layout
-  if (rc == ESLB_OK) {
-    set_step(nsteps);
-    rc = launch_layout(c, cot, fbar, true);
-  }
-  // 3) segments in reverse: recompute the step states, then each step's stage inputs
-  for (int64_t i = nseg - 1; i >= 0 && rc == ESLB_OK; --i) {
-    const int64_t s0 = i * ck, s1 = std::min<int64_t>(nsteps, s0 + ck);
-    set_step(s0);
-    rc = copy(seg, ckp + (size_t)i * sd);
-    for (int64_t j = 1; j < s1 - s0 && rc == ESLB_OK; ++j) {
-      rc = copy(seg + (size_t)j * sd, seg + (size_t)(j - 1) * sd);
-      if (rc == ESLB_OK) rc = eslb_step(c, seg + (size_t)j * sd, 1);
-    }
-    for (int64_t s = s1 - 1; s >= s0 && rc == ESLB_OK; --s) {
-      set_step(s);
-      rc = copy(run, seg + (size_t)(s - s0) * sd);
-      for (int p = 0; p < npass && rc == ESLB_OK; ++p) {
-        add_offsets(c, c->passes[p].shift);
-        rc = copy(stin + (size_t)p * sd, run);
-        if (rc == ESLB_OK) {
-          if (c->passes[p].op == PASS_PROJECT) {
-            const double keep = c->phys.omega;
-            c->phys.omega = 1.0;
-            rc = launch_stage(c, run, 0);
-            c->phys.omega = keep;
-          } else {
-            rc = launch_stage(c, run, c->pb.relax);
-          }
-        }
-      }
-      for (int p = npass - 1; p >= 0 && rc == ESLB_OK; --p) {
-        rc = launch_adjoint_stage(c, stin + (size_t)p * sd, cot, c->passes[p].op);
-        add_offsets(c, -c->passes[p].shift);
-      }
-    }
-  }
-  // 4) cotangent of f0 back to logical layout
-  set_step(0);
-  if (rc == ESLB_OK) rc = launch_layout(c, cot, fbar, false);
+  // forward sweep from a copy of f0, keeping a checkpoint every ck steps
+  int rc = hip_check(c, hipMemcpyAsync(wk, f0, sb, hipMemcpyDeviceToDevice, c->stream), "device copy");
+  if (rc == ESLB_OK) rc = eslb_step_checkpointed(c, wk, nsteps, ck, ckp);
   for (int k = 0; k < 4; ++k) c->off[k] = o0[k];
-  return rc;
+  if (rc != ESLB_OK) return rc;
+  return adjoint_sweep(c, ckp, nsteps, ck, fbar, wk, taped);
 }
 
 }  // extern "C"

@@ -767,9 +767,12 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
 enum : unsigned { FLAG_INADMISSIBLE = 1u, FLAG_NAN = 2u, FLAG_FALLBACK = 4u, FLAG_SUBCHAR = 8u };
 
 // Relax one node in place.  mode 0: omega = P.omega (eq. relaxationDiscretizationOmega);
-// mode 1: entropy-limited omega (eq. variableOmegaProblem).  Returns omega used.
+// mode 1: entropy-limited omega (eq. variableOmegaProblem).  Returns omega used;
+// lam_out = the lambda = omega - 1 of the update, NaN where the root search fell
+// back to omega = 1 (the adjoint then drops the grad-omega term).
 template <class S>
-__device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags) {
+__device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
+                                    double& lam_out) {
   constexpr int Q = S::Q, M = S::M;
   double u[M], feq[Q][M], d[Q][M], dmax, fsc;
   node_split<S>(f, u, feq, d, dmax, fsc, P);
@@ -779,6 +782,7 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
     for (int k = 0; k < Q; ++k)
 #pragma unroll
       for (int m = 0; m < M; ++m) f[k][m] = om1 * f[k][m] + om * feq[k][m];
+    lam_out = om - 1.0;
     return om;
   }
   typename S::Node c;
@@ -809,7 +813,14 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
   for (int k = 0; k < Q; ++k)
 #pragma unroll
     for (int m = 0; m < M; ++m) f[k][m] = feq[k][m] - lam * d[k][m];
+  lam_out = fallback ? NAN : lam;
   return lam + 1.0;
+}
+
+template <class S>
+__device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags) {
+  double unused;
+  return relax_node<S>(f, mode, P, flags, unused);
 }
 
 // sum_k J_k^T y_k, J_k = d f_k^eq / du = w I + sigma_k (d phi^{n_k}/du) / (2V).
@@ -906,6 +917,26 @@ __device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, con
       }
       grad = !fallback;
     }
+    om = lam + 1.0;
+  }
+}
+
+// adjoint_root with the forward pass's lambda given (recorded by the stage
+// kernel that produced this pass's output from h): no root search.
+template <class S>
+__device__ inline void adjoint_taped(const double (&h)[S::Q][S::M], int mode, double lam_rec, const Phys& P,
+                                     double (&u)[S::M], double (&d)[S::Q][S::M], double& lam, double& om,
+                                     bool& grad) {
+  constexpr int Q = S::Q, M = S::M;
+  double feq[Q][M], dmax, fsc;
+  node_split<S>(h, u, feq, d, dmax, fsc, P);
+  om = P.omega;
+  lam = P.omega - 1.0;
+  grad = false;
+  if (mode == 1) {
+    const bool fallback = isnan(lam_rec);
+    lam = fallback ? 0.0 : lam_rec;
+    grad = !fallback && (dmax != 0.0);
     om = lam + 1.0;
   }
 }

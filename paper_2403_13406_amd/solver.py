@@ -205,11 +205,61 @@ class Solver:
                                                                          ctypes.byref(b)))
         return b.value
 
-    def adjoint(self, f0, nsteps, ckpt_every, fbar, work=None):
-        """fbar (logical, cotangent of the state after nsteps) -> cotangent of f0, in place."""
+    def adjoint_tape_bytes(self, nsteps, ckpt_every):
+        b = ctypes.c_size_t()
+        _check(self.lib, self.ctx, self.lib.eslb_adjoint_tape_bytes(self.ctx, int(nsteps), int(ckpt_every),
+                                                                    ctypes.byref(b)))
+        return b.value
+
+    def checkpoint_bytes(self, nsteps, ckpt_every):
+        b = ctypes.c_size_t()
+        _check(self.lib, self.ctx, self.lib.eslb_checkpoint_bytes(self.ctx, int(nsteps), int(ckpt_every),
+                                                                  ctypes.byref(b)))
+        return b.value
+
+    def step_checkpointed(self, f, nsteps, ckpt_every, ckpt=None):
+        """nsteps steps on f, keeping the state every ckpt_every steps (returns the checkpoints)."""
+        import torch
+        nseg = -(-int(nsteps) // int(ckpt_every))
+        if ckpt is None:
+            ckpt = torch.empty((max(nseg, 1),) + self.state_shape, dtype=torch.float64, device="cuda")
+        if ckpt.dtype != torch.float64 or not ckpt.is_cuda or not ckpt.is_contiguous() or \
+                ckpt.numel() * 8 < self.checkpoint_bytes(nsteps, ckpt_every):
+            raise ValueError("checkpoint buffer too small")
+        _check(self.lib, self.ctx, self.lib.eslb_step_checkpointed(self.ctx, self._ptr(f, self.state_shape),
+                                                                   int(nsteps), int(ckpt_every),
+                                                                   ctypes.c_void_p(ckpt.data_ptr())))
+        return ckpt
+
+    def adjoint_checkpointed(self, ckpt, nsteps, ckpt_every, fbar, work=None, tape="auto"):
+        """Solver.adjoint from the checkpoints of step_checkpointed (offsets as at its start)."""
+        import torch
+        cb = self.checkpoint_bytes(nsteps, ckpt_every)
+        if ckpt.dtype != torch.float64 or not ckpt.is_cuda or not ckpt.is_contiguous() or ckpt.numel() * 8 < cb:
+            raise ValueError("checkpoint buffer too small")
+        nb = self.adjoint_workspace_bytes(nsteps, ckpt_every) - cb
+        if work is None:
+            nt = self.adjoint_tape_bytes(nsteps, ckpt_every) - cb
+            if tape is True or (tape == "auto" and nt <= torch.cuda.mem_get_info()[0] // 2):
+                nb = max(nb, nt)
+            work = torch.empty(max(nb, 8), dtype=torch.uint8, device="cuda")
+        _check(self.lib, self.ctx, self.lib.eslb_adjoint_checkpointed(
+            self.ctx, ctypes.c_void_p(ckpt.data_ptr()), int(nsteps), int(ckpt_every),
+            self._ptr(fbar, self.state_shape), ctypes.c_void_p(work.data_ptr()), work.numel()))
+        return fbar
+
+    def adjoint(self, f0, nsteps, ckpt_every, fbar, work=None, tape="auto"):
+        """fbar (logical, cotangent of the state after nsteps) -> cotangent of f0, in place.
+
+        work=None allocates the workspace: the taped size (each step recomputed once
+        instead of twice) when tape is True, or when tape is "auto" and it takes at
+        most half of the free device memory; otherwise the minimal size."""
         import torch
         nb = self.adjoint_workspace_bytes(nsteps, ckpt_every)
         if work is None:
+            nt = self.adjoint_tape_bytes(nsteps, ckpt_every)
+            if tape is True or (tape == "auto" and nt <= torch.cuda.mem_get_info()[0] // 2):
+                nb = max(nb, nt)
             work = torch.empty(max(nb, 8), dtype=torch.uint8, device="cuda")
         _check(self.lib, self.ctx, self.lib.eslb_adjoint(self.ctx, self._ptr(f0, self.state_shape), int(nsteps),
                                                          int(ckpt_every), self._ptr(fbar, self.state_shape),

@@ -79,6 +79,68 @@ def test_checkpoint_interval_does_not_change_the_result():
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("name,scheme,nsteps,ck", [("euler2d", 1, 5, 2), ("sw2d", 2, 3, 2), ("euler2d", 3, 3, 5),
+                                                    ("sw1d", 1, 4, 4)])
+def test_taped_and_recomputing_workspaces(name, scheme, nsteps, ck):
+    """With the taped workspace (one recomputation per segment) eslb_adjoint gives the
+    bits of the minimal workspace (per-step recomputation); both match the oracle's
+    reverse sweep, for Scheme I and the projected Schemes II and III."""
+    import torch
+    w = small(name)
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    u = initial_u(w)
+    s = solver_for(w, "entropic", scheme=scheme)
+    f0 = s.init_equilibrium(to_gpu(u))
+    fbarT = np.random.default_rng(33).standard_normal(f0.shape)
+    nmin, ntape = s.adjoint_workspace_bytes(nsteps, ck), s.adjoint_tape_bytes(nsteps, ck)
+    outs = []
+    for nb in (nmin, ntape):
+        fb = to_gpu(fbarT)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        s.adjoint(f0, nsteps, ck, fb, work=work)
+        assert s.sync() == 0
+        outs.append(to_host(fb))
+    assert np.array_equal(outs[0], outs[1])
+    want = adjoint_run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u), nsteps, fbarT,
+                       scheme=scheme)
+    err = componentwise_error(outs[1], want)
+    assert max(err) <= 1e-9, err
+    for m in range(want.shape[1]):
+        l2 = np.linalg.norm(outs[1][:, m] - want[:, m]) / np.linalg.norm(want[:, m])
+        assert l2 <= MULTI_STEP_L2, (m, l2)
+
+
+@pytest.mark.parametrize("nsteps,ck", [(5, 2), (4, 4), (3, 7)])
+def test_adjoint_from_forward_checkpoints(nsteps, ck):
+    """eslb_step_checkpointed + eslb_adjoint_checkpointed: the forward state of
+    eslb_step and the cotangent bits of eslb_adjoint, with either workspace."""
+    import torch
+    w = small("euler2d")
+    s = solver_for(w, "entropic")
+    f0 = s.init_equilibrium(to_gpu(initial_u(w)))
+    fbarT = to_gpu(np.random.default_rng(34).standard_normal(f0.shape))
+    want = fbarT.clone()
+    s.adjoint(f0, nsteps, ck, want)
+    f_plain = f0.clone()
+    s.step(f_plain, nsteps)
+    s.offsets = [0] * s.q
+    f = f0.clone()
+    ckpt = s.step_checkpointed(f, nsteps, ck)
+    off = s.offsets
+    assert s.sync() == 0
+    assert torch.equal(f, f_plain)
+    s.offsets = [0] * s.q
+    cb = s.checkpoint_bytes(nsteps, ck)
+    assert ckpt.numel() * 8 == cb
+    for nb in (s.adjoint_workspace_bytes(nsteps, ck) - cb, s.adjoint_tape_bytes(nsteps, ck) - cb):
+        fb = fbarT.clone()
+        s.adjoint_checkpointed(ckpt, nsteps, ck, fb, work=torch.empty(nb, dtype=torch.uint8, device="cuda"))
+        assert s.sync() == 0
+        assert s.offsets == [0] * s.q
+        assert torch.equal(fb, want)
+    assert off != [0] * s.q  # the run moved the offsets (they were restored above)
+
+
 def test_autograd_misfit_gradient_against_oracle_and_finite_differences():
     """dL/dU0 for L = 1/2 |U(T) - U_target|^2 through the torch.autograd.Function."""
     import torch
