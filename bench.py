@@ -41,6 +41,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + % HBM peak per 4th-order step; batched & adjoint vs plain same GPU"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (FMA counted as two)
+VALU_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9 / 1e12   # lane-slots/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 
 
 def make_workload(name, size):
@@ -149,6 +150,13 @@ def bench_single(args, torch):
         roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "traffic": hbm["traffic"],
                     "flop_per_node": valu["fp64_flop_per_node"]}
+        # the same pass against the VALU issue rate: every VALU instruction takes a
+        # SIMD's 16 lanes four cycles per wave, an FP64 transcendental four times that
+        li = valu["lane_instructions_per_node"]
+        slots = li["SQ_INSTS_VALU"] + 3.0 * li["SQ_INSTS_VALU_TRANS_F64"]
+        issue = slots * w.cells / avg_launch_s / 1e12
+        roofline["valu_issue"] = {"achieved": round(issue, 2), "peak": VALU_ISSUE_PEAK, "unit": "T lane-slots/s",
+                                  "frac": round(issue / VALU_ISSUE_PEAK, 4), "slots_per_node": slots}
     else:
         roofline = hbm
     rec = {
