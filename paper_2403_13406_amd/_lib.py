@@ -13,6 +13,7 @@ P = ctypes.POINTER
 D1Q2, D2Q4 = 1, 2
 ADVECTION, BURGERS, SHALLOW_WATER, EULER = 0, 1, 2, 3
 OMEGA_FIXED, OMEGA_ENTROPIC = 0, 1
+FUSE_OFF, FUSE_AUTO, FUSE_ALWAYS = 0, 1, 2
 OK = 0
 ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM, ERR_INADMISSIBLE, ERR_NAN = -1, -2, -3, -4, -6, -7
 WARN_OMEGA_FALLBACK, WARN_T_NOT_MULTIPLE, WARN_SUBCHARACTERISTIC = 1, 2, 3
@@ -55,6 +56,9 @@ _SIGNATURES = {
     "eslb_init_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "eslb_adjoint_workspace_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
     "eslb_adjoint_tape_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
+    "eslb_set_step_workspace": (c_int32, [c_void_p, c_void_p, ctypes.c_size_t]),
+    "eslb_fused_step_available": (c_int32, [c_void_p, P(c_int32)]),
+    "eslb_set_fusion": (c_int32, [c_void_p, c_int32]),
     "eslb_checkpoint_bytes": (c_int32, [c_void_p, c_int64, c_int64, P(ctypes.c_size_t)]),
     "eslb_step_checkpointed": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p]),
     "eslb_adjoint_checkpointed": (c_int32, [c_void_p, c_void_p, c_int64, c_int64, c_void_p, c_void_p,

@@ -451,6 +451,108 @@ __global__ __launch_bounds__(run_lds_threads<S>()) void k_run_lds(Grid g, Phys P
   }
 }
 
+// One composed step of a D1Q2 problem per launch, every pass through LDS.  Block
+// b owns the output cells [b L, b L + L) and loads the window of W = L + 2H cells
+// around them (H: the step's dependency halo, from the schedule).  Inside the
+// window population k of logical cell a - H + j sits at index j - sign_k o after
+// the passes have moved it by o cells; pass p relaxes the cells whose two
+// populations are still exact (the exact index ranges shrink by the shift at every
+// pass and are tracked as block-uniform bounds), and the owned cells are stored in
+// the layout of the offsets after the step.  Reads src, writes dst (no overlap:
+// neighbouring windows overlap, so the step cannot be done in place).
+struct FusedPlan {
+  int npass;
+  int trailing;
+  int shift[32];
+  int op[32];   // 0: relax with the context's omega, 1: projection R_1
+  int L, H;     // owned cells per block, halo cells on each side
+};
+
+// 256 threads and 32 KiB windows: several blocks per CU, so one block's barrier
+// waits overlap another's work (measured: 512 threads and 64 KiB windows were
+// 15-30% slower on every 1D system).
+constexpr int kFusedThreads = 256;
+constexpr int kFusedWindowBytes = 32768;
+
+template <class S>
+__global__ __launch_bounds__(kFusedThreads, S::kStageBlocks) void k_step_fused_1d(const double* __restrict__ src,
+                                                                    double* __restrict__ dst, int nx, int sh_in0,
+                                                                    int sh_in1, int sh_out0, int sh_out1, Phys P,
+                                                                    int mode, FusedPlan fp, DevStats* st) {
+  constexpr int M = S::M;
+  extern __shared__ double lds[];
+  const int L = fp.L, H = fp.H, W = L + 2 * H;
+  const long long a = (long long)blockIdx.x * L;
+  const int Lb = (nx - a < L) ? (int)(nx - a) : L;
+  const int Wb = Lb + 2 * H;
+  for (int j = threadIdx.x; j < Wb; j += blockDim.x) {
+    long long x = (a - H + j) % nx;
+    if (x < 0) x += nx;
+    int s0 = (int)x + sh_in0, s1 = (int)x + sh_in1;
+    if (s0 >= nx) s0 -= nx;
+    if (s1 >= nx) s1 -= nx;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      lds[m * W + j] = src[(long long)m * nx + s0];
+      lds[(M + m) * W + j] = src[(long long)(M + m) * nx + s1];
+    }
+  }
+  unsigned flags = 0;
+  unsigned long long nfall = 0;
+  int o = 0;
+  int lo0 = 0, hi0 = Wb, lo1 = 0, hi1 = Wb;  // exact index ranges of populations 0 and 1
+  for (int p = 0; p < fp.npass; ++p) {
+    o += fp.shift[p];
+    Phys Pp = P;
+    int md = mode;
+    if (fp.op[p]) {
+      Pp.omega = 1.0;
+      md = 0;
+    }
+    const int rlo = max(lo0 + o, lo1 - o), rhi = min(hi0 + o, hi1 - o);
+    __syncthreads();
+    for (int j = rlo + (int)threadIdx.x; j < rhi; j += blockDim.x) {
+      double f[2][M];
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        f[0][m] = lds[m * W + j - o];
+        f[1][m] = lds[(M + m) * W + j + o];
+      }
+      unsigned nf = 0;
+      relax_node<S>(f, md, Pp, nf);
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (!isfinite(f[0][m]) || !isfinite(f[1][m])) nf |= FLAG_NAN;
+        lds[m * W + j - o] = f[0][m];
+        lds[(M + m) * W + j + o] = f[1][m];
+      }
+      flags |= nf;
+      nfall += (nf & FLAG_FALLBACK) ? 1ull : 0ull;
+    }
+    lo0 = rlo - o;
+    hi0 = rhi - o;
+    lo1 = rlo + o;
+    hi1 = rhi + o;
+  }
+  o += fp.trailing;
+  __syncthreads();
+  for (int t = threadIdx.x; t < Lb; t += blockDim.x) {
+    const int x = (int)a + t, j = H + t;
+    int s0 = x + sh_out0, s1 = x + sh_out1;
+    if (s0 >= nx) s0 -= nx;
+    if (s1 >= nx) s1 -= nx;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      dst[(long long)m * nx + s0] = lds[m * W + j - o];
+      dst[(long long)(M + m) * nx + s1] = lds[(M + m) * W + j + o];
+    }
+  }
+  if (flags) {
+    atomicOr(&st->flags, flags);
+    if (nfall) atomicAdd(&st->n_fallback, nfall);
+  }
+}
+
 // Diagnostics, pass 1: per-block partial sums in a fixed tree order.
 // Layout of a block's partials: mass[M], micro, macro (NV = M + 2 doubles).
 constexpr int kDiagThreads = 256;
@@ -955,6 +1057,80 @@ int run_small(eslb_ctx* c, double* f, int64_t nsteps) {
   return rc;
 }
 
+// Halo of the fused D1Q2 step: the smallest H for which the owned cells of a
+// window are exact after the step (the exact-range recurrence of k_step_fused_1d,
+// which does not depend on H: ranges are kept as offsets from both window ends).
+int fused_halo(const eslb_ctx* c) {
+  int o = 0, lo0 = 0, ho0 = 0, lo1 = 0, ho1 = 0;  // [lo, Wb + ho)
+  for (const Pass& ps : c->passes) {
+    o += (int)ps.shift;
+    const int rlo = std::max(lo0 + o, lo1 - o), rho = std::min(ho0 + o, ho1 - o);
+    lo0 = rlo - o;
+    ho0 = rho - o;
+    lo1 = rlo + o;
+    ho1 = rho + o;
+  }
+  o += c->trailing;
+  // owned cells j in [H, H + Lb) need j - o in [lo0, Wb + ho0) and j + o in [lo1, Wb + ho1)
+  return std::max({0, lo0 + o, lo1 - o, -o - ho0, o - ho1});
+}
+
+// Whether eslb_step takes the fused kernel (given a workspace).  ESLB_FUSE_AUTO:
+// where it measured faster than the per-pass path -- fixed omega (the per-pass
+// path is bound by memory and launches: 3.6-4.4x) and the entropic scalar systems
+// (Burgers 2^22: 6%); the entropic shallow-water pass is arithmetic-bound and its
+// fused version 4% slower (the barriers between passes), so it stays per pass.
+bool fused_active(const eslb_ctx* c) {
+  if (c->fused_L <= 0 || c->small_run || c->fuse == ESLB_FUSE_OFF) return false;
+  if (c->fuse == ESLB_FUSE_ALWAYS) return true;
+  return c->pb.relax == ESLB_OMEGA_FIXED || c->kind != KIND_SW1;
+}
+
+// Composed steps of a D1Q2 problem, one fused kernel per step, alternating
+// between f and the step workspace (a final copy when the count is odd).
+int run_fused(eslb_ctx* c, double* f, int64_t nsteps) {
+  FusedPlan fp;
+  fp.npass = (int)c->passes.size();
+  fp.trailing = c->trailing;
+  for (int p = 0; p < fp.npass; ++p) {
+    fp.shift[p] = (int)c->passes[p].shift;
+    fp.op[p] = c->passes[p].op == PASS_PROJECT ? 1 : 0;
+  }
+  fp.H = c->fused_H;
+  fp.L = c->fused_L;
+  const int nx = c->pb.nx;
+  const unsigned nblk = (unsigned)((nx + fp.L - 1) / fp.L);
+  const size_t lds = (size_t)2 * c->M * (fp.L + 2 * fp.H) * sizeof(double);
+  const long long net = net_shift(c);
+  Phys P = c->phys;
+  const int mode = c->pb.relax;
+  double* buf[2] = {f, c->step_work};
+  int cur = 0, rc = ESLB_OK;
+  for (int64_t s = 0; s < nsteps && rc == ESLB_OK; ++s) {
+    const Grid gi = make_grid(c, buf[cur]);
+    add_offsets(c, net);
+    const Grid go = make_grid(c, buf[1 - cur]);
+#define CALL(S, D)                                                                                            \
+  hipLaunchKernelGGL((k_step_fused_1d<S>), dim3(nblk), dim3(kFusedThreads), lds, c->stream, buf[cur],         \
+                     buf[1 - cur], nx, gi.sh[0], gi.sh[1], go.sh[0], go.sh[1], P, mode, fp, c->st)
+    switch (c->kind) {
+      case KIND_ADV1: CALL(Advection<1>, 1); break;
+      case KIND_BUR1: CALL(Burgers<1>, 1); break;
+      case KIND_SW1: CALL(ShallowWater<1>, 1); break;
+      default: break;
+    }
+#undef CALL
+    rc = hip_check(c, hipGetLastError(), "fused step kernel launch");
+    cur = 1 - cur;
+  }
+  if (rc == ESLB_OK && cur == 1) {
+    size_t sb = 0;
+    eslb_state_bytes(c, &sb);
+    rc = hip_check(c, hipMemcpyAsync(f, c->step_work, sb, hipMemcpyDeviceToDevice, c->stream), "device copy");
+  }
+  return rc;
+}
+
 }  // namespace eslb
 
 // ------------------------------------------------------------------ C ABI
@@ -1001,6 +1177,15 @@ int eslb_create(const eslb_problem* p, void* stream, eslb_ctx** out) {
   build_schedule(c);
   // whole run in one workgroup's LDS when the state is at most 64 KiB
   c->small_run = ((size_t)q * M * (size_t)p->nx * p->ny * sizeof(double) <= 65536) && c->passes.size() <= 32;
+  // fused D1Q2 steps: windows of kFusedWindowBytes of LDS, at least 64 owned cells each
+  if (d == 1 && c->passes.size() <= 32) {
+    const int H = fused_halo(c);
+    const int W = kFusedWindowBytes / (2 * M * (int)sizeof(double));
+    if (W - 2 * H >= 64) {
+      c->fused_H = H;
+      c->fused_L = W - 2 * H;
+    }
+  }
   c->diag_blocks = 1024;
   const int nv = M + 2;
   hipError_t e = hipMalloc(&c->st, sizeof(DevStats));
@@ -1082,6 +1267,7 @@ int eslb_init_equilibrium(eslb_ctx* c, const double* u, double* f) {
 int eslb_step(eslb_ctx* c, double* f, int64_t nsteps) {
   if (!c || !f || nsteps < 0) return set_err(c, ESLB_ERR_INVALID_ARG, "bad argument to eslb_step");
   if (nsteps > 0 && c->small_run && !c->track) return run_small(c, f, nsteps);
+  if (nsteps > 0 && fused_active(c) && c->step_work && !c->track) return run_fused(c, f, nsteps);
   for (int64_t s = 0; s < nsteps; ++s) {
     for (const Pass& ps : c->passes) {
       const int rc = run_pass(c, f, ps.shift, ps.op);
@@ -1140,6 +1326,28 @@ int eslb_get_offsets(const eslb_ctx* c, int64_t* o) {
 int eslb_set_offsets(eslb_ctx* c, const int64_t* o) {
   if (!c || !o) return ESLB_ERR_INVALID_ARG;
   for (int k = 0; k < c->q; ++k) c->off[k] = o[k];
+  return ESLB_OK;
+}
+
+int eslb_set_step_workspace(eslb_ctx* c, void* work, size_t bytes) {
+  if (!c) return ESLB_ERR_INVALID_ARG;
+  size_t sb = 0;
+  eslb_state_bytes(c, &sb);
+  if (work && bytes < sb) return set_err(c, ESLB_ERR_INVALID_ARG, "step workspace smaller than one state");
+  c->step_work = (double*)work;
+  c->step_work_bytes = work ? bytes : 0;
+  return ESLB_OK;
+}
+
+int eslb_set_fusion(eslb_ctx* c, int32_t policy) {
+  if (!c || policy < ESLB_FUSE_OFF || policy > ESLB_FUSE_ALWAYS) return ESLB_ERR_INVALID_ARG;
+  c->fuse = policy;
+  return ESLB_OK;
+}
+
+int eslb_fused_step_available(const eslb_ctx* c, int32_t* yes) {
+  if (!c || !yes) return ESLB_ERR_INVALID_ARG;
+  *yes = fused_active(c) ? 1 : 0;
   return ESLB_OK;
 }
 

@@ -77,5 +77,9 @@ struct eslb_ctx {
   int diag_blocks = 0;
   int track = 0;
   bool small_run = false;  // whole run in one workgroup's LDS (small states)
+  int fused_L = 0, fused_H = 0;  // fused D1Q2 step: owned cells per block, halo (0: not available)
+  int fuse = ESLB_FUSE_AUTO;     // eslb_set_fusion policy
+  double* step_work = nullptr;   // caller-owned workspace of one state for the fused steps
+  size_t step_work_bytes = 0;
   std::string err;
 };

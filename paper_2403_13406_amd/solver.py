@@ -51,7 +51,10 @@ class Solver:
     """One problem on one device stream (eslb_create .. eslb_destroy)."""
 
     def __init__(self, lattice, system, nx, ny=1, V=1.0, dx=None, kappa=1, relax="entropic", omega=2.0,
-                 scheme=1, param=(0.0,), stream=None):
+                 scheme=1, param=(0.0,), stream=None, fused="auto"):
+        """fused: policy of the fused D1Q2 step ("auto": where it is the faster path,
+        True: always, False: never); a workspace of one state is attached when the
+        policy takes it."""
         import torch
         self.lib = L.load()
         self.problem = make_problem(lattice, system, nx, ny, V, dx, kappa, relax, omega, scheme, param)
@@ -67,6 +70,26 @@ class Solver:
         self.lib.eslb_dims(ctx, ctypes.byref(M), ctypes.byref(q))
         self.M, self.q = M.value, q.value
         self.nx, self.ny = int(nx), int(ny)
+        self.step_work = None
+        self.set_fused(fused)
+
+    def set_fused(self, policy="auto"):
+        """Fusion policy ("auto", True, False) and the workspace it needs; True when eslb_step
+        now takes the fused kernel."""
+        import torch
+        code = {"auto": L.FUSE_AUTO, True: L.FUSE_ALWAYS, False: L.FUSE_OFF}[policy]
+        _check(self.lib, self.ctx, self.lib.eslb_set_fusion(self.ctx, code))
+        avail = ctypes.c_int32()
+        self.lib.eslb_fused_step_available(self.ctx, ctypes.byref(avail))
+        if avail.value:
+            if self.step_work is None:
+                self.step_work = torch.empty(self.state_shape, dtype=torch.float64, device="cuda")
+            _check(self.lib, self.ctx, self.lib.eslb_set_step_workspace(
+                self.ctx, ctypes.c_void_p(self.step_work.data_ptr()), self.step_work.numel() * 8))
+            return True
+        _check(self.lib, self.ctx, self.lib.eslb_set_step_workspace(self.ctx, None, 0))
+        self.step_work = None
+        return False
 
     # -- lifetime
     def close(self):

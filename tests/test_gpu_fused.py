@@ -1,0 +1,105 @@
+"""Fused D1Q2 step (one kernel per composed step, all passes through LDS) against the
+per-pass path, bit for bit, and against the oracle at sizes that span several blocks
+with a ragged last block."""
+import numpy as np
+import pytest
+
+from gpu_common import PARITY_RTOL, componentwise_error, oracle_system, to_gpu, to_host
+from oracle.scheme import Relaxer, run
+from oracle.systems import equilibrium
+from paper_2403_13406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# owned cells per block: 32 KiB of LDS per window minus the halo (36 cells for Scheme I)
+L_SW, L_SCALAR = 1024 - 72, 2048 - 72
+
+
+def start_state(system, n, seed):
+    rng = np.random.default_rng(seed)
+    x = np.arange(n) / n
+    if system == "shallow_water":
+        h = 1.0 + 0.1 * np.sin(2 * np.pi * x) + 0.02 * rng.standard_normal(n) * 0.01
+        return np.stack([h, 0.05 * np.cos(2 * np.pi * x)])[:, None, :]
+    return (0.5 + 0.25 * np.sin(2 * np.pi * x) + 0.01 * np.sin(6 * np.pi * x + rng.uniform()))[None, None, :]
+
+
+# states above 64 KiB (smaller ones run in one workgroup), several blocks, ragged last block
+CASES = [("shallow_water", (9.81,), 4.5, 3 * L_SW + 123), ("burgers", (1.0,), 2.0, 3 * L_SCALAR + 5),
+         ("advection", (0.7,), 1.0, 3 * L_SCALAR + 1), ("shallow_water", (9.81,), 4.5, 5000)]
+
+
+@pytest.mark.parametrize("system,param,V,n", CASES)
+@pytest.mark.parametrize("relax,scheme", [("entropic", 1), ("fixed", 1), ("fixed", 2), ("fixed", 3),
+                                          ("entropic", 3)])
+def test_fused_step_equals_per_pass_path(system, param, V, n, relax, scheme):
+    import torch
+
+    from paper_2403_13406_amd import Solver
+    a = Solver("D1Q2", system, n, 1, V=V, relax=relax, param=param, scheme=scheme, fused=True)
+    b = Solver("D1Q2", system, n, 1, V=V, relax=relax, param=param, scheme=scheme, fused=False)
+    assert a.step_work is not None and b.step_work is None
+    u = to_gpu(start_state(system, n, 40))
+    fa, fb = a.init_equilibrium(u), b.init_equilibrium(u)
+    for k in (1, 2, 3):    # odd counts end with the copy back from the workspace
+        a.step(fa, k)
+        b.step(fb, k)
+        assert a.sync() == 0 and b.sync() == 0
+        assert a.offsets == b.offsets
+        assert torch.equal(fa, fb), (k, float((fa - fb).abs().max()))
+
+
+@pytest.mark.parametrize("system,param,V,n", CASES[:2])
+def test_fused_step_against_oracle(system, param, V, n):
+    from paper_2403_13406_amd import Solver
+    lat, sys = oracle_system("D1Q2", system, param)
+    u = start_state(system, n, 41)
+    s = Solver("D1Q2", system, n, 1, V=V, relax="entropic", param=param, fused=True)
+    assert s.step_work is not None
+    f = s.init_equilibrium(to_gpu(u))
+    s.step(f, 3)
+    assert s.sync() == 0
+    want = run(Relaxer(lat, sys, V, "entropic"), equilibrium(lat, sys, V, u), 3)
+    assert max(componentwise_error(to_host(s.gather(f)), want)) <= PARITY_RTOL
+
+
+def test_fused_step_full_size_sw1d_sampled():
+    """The 2^20-cell shallow-water workload: fused against per-pass after 2 steps (bitwise),
+    and sampled cells against the oracle on a periodic window of 2 x 36 + 1 cells per step."""
+    import torch
+
+    from paper_2403_13406_amd import Solver
+    w = W.sw1d()
+    a = Solver(w.lattice, w.system, w.nx, 1, V=w.V, relax="entropic", param=w.param, fused=True)
+    b = Solver(w.lattice, w.system, w.nx, 1, V=w.V, relax="entropic", param=w.param, fused=False)
+    u = w.initial_state()
+    fa, fb = a.init_equilibrium(to_gpu(u)), b.init_equilibrium(to_gpu(u))
+    a.step(fa, 2)
+    b.step(fb, 2)
+    assert a.sync() == 0 and b.sync() == 0
+    assert torch.equal(fa, fb)
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    g = to_host(a.gather(fa))
+    half = 2 * 36 + 8
+    for x in np.random.default_rng(42).integers(0, w.nx, 6):
+        idx = (np.arange(-half, half + 1) + x) % w.nx
+        want = run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u[:, :, idx]), 2)
+        got = g[:, :, :, idx]
+        c = half
+        scale = np.max(np.abs(want[:, :, :, c]))
+        assert np.max(np.abs(got[:, :, :, c] - want[:, :, :, c])) <= PARITY_RTOL * scale
+
+
+def test_fusion_policy():
+    """"auto" takes the fused step for fixed omega and the entropic scalar systems, not for the
+    entropic shallow-water pass; False never; True always (for grids above one workgroup)."""
+    from paper_2403_13406_amd import Solver
+    n = 6000
+    assert Solver("D1Q2", "shallow_water", n, 1, V=4.5, relax="entropic", param=(9.81,)).step_work is None
+    assert Solver("D1Q2", "shallow_water", n, 1, V=4.5, relax="fixed", param=(9.81,)).step_work is not None
+    assert Solver("D1Q2", "burgers", n, 1, V=2.0, relax="entropic", param=(1.0,)).step_work is not None
+    assert Solver("D1Q2", "burgers", n, 1, V=2.0, relax="fixed", param=(1.0,), fused=False).step_work is None
+    assert Solver("D1Q2", "shallow_water", n, 1, V=4.5, relax="entropic", param=(9.81,),
+                  fused=True).step_work is not None
+    assert Solver("D1Q2", "burgers", 1000, 1, V=2.0, param=(1.0,), fused=True).step_work is None  # one workgroup
+    assert Solver("D2Q4", "burgers", 64, 64, V=2.0, param=(1.0, 0.5), fused=True).step_work is None
