@@ -21,6 +21,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 #include <math.h>
 
 namespace eslb {
@@ -143,6 +145,8 @@ template <int D> struct Advection {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
+  using Fast = Advection;  // no deferred branch (see ShallowWater::Fast)
+  __device__ static bool pending(const Node&) { return false; }
   __device__ static double skip_limit(const Node&, const Phys&) { return -1.0; }  // no skip measure
   __device__ static double a(int j, const Phys& P) { return j == 0 ? P.p0 : P.p1; }
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) { phi[0] = a(j, P) * u[0]; }
@@ -177,6 +181,8 @@ template <int D> struct Burgers {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
+  using Fast = Burgers;  // no deferred branch (see ShallowWater::Fast)
+  __device__ static bool pending(const Node&) { return false; }
   __device__ static double skip_limit(const Node&, const Phys&) { return -1.0; }  // no skip measure
   __device__ static double b(int j, const Phys& P) { return j == 0 ? P.p0 : P.p1; }
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) { phi[0] = 0.5 * b(j, P) * u[0] * u[0]; }
@@ -297,10 +303,22 @@ __device__ inline double sw_branch_root(double P0, double P1, double P2, double 
   return best;
 }
 
+template <int D> struct ShallowWaterFast;
+
 template <int D> struct ShallowWater {
   static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int M = D + 1, Q = Lat<D>::Q;
-  struct Node { double h, vel[D]; };
+  // rule: set by the Fast variant's evaluations where Newton alone did not give
+  // the branch root (the node is then relaxed again with the branch rule)
+  struct Node { double h, vel[D]; mutable bool rule; };
+  // Fast: the same evaluations without the branch rule (sw_branch_root).  The
+  // rule is needed far from the cell state only; inlined into every evaluation it
+  // costs the hot path registers and code, so relax_node runs the root search
+  // with Fast and, on the rare nodes that flag it, once more with the rule
+  // (measured on D2Q4: SW2D pass -1%, batched ensemble -2.6%; on D1Q2 it gained
+  // nothing, so there the rule stays inline).
+  using Fast = typename std::conditional<D == 2, ShallowWaterFast<D>, ShallowWater<D>>::type;
+  __device__ static bool pending(const Node&) { return false; }  // this variant applies the rule itself
   // skip measure of the predictor (see Euler2): |dh|/h, |e_1|/f_1 and
   // |dn|/W at t = -1 against 2^-8 m^2, m = 1 - g h / W_min^2; on oracle roots the
   // prediction stays at the rounding floor up to z / m^2 ~ 2^-7 (D = 1 and 2)
@@ -321,6 +339,7 @@ template <int D> struct ShallowWater {
   }
   __device__ static bool prepare(const double* u, Node& c, const Phys&) {
     c.h = u[0];
+    c.rule = false;
     const double ih = rcp(u[0]);
 #pragma unroll
     for (int i = 0; i < D; ++i) c.vel[i] = u[1 + i] * ih;
@@ -351,7 +370,7 @@ template <int D> struct ShallowWater {
 #pragma unroll
     for (int l = 0; l < D; ++l) out[1 + l] = vj * z[1 + l] + (l == j ? z[0] + zv : 0.0);
   }
-  template <int k, bool DV>
+  template <int k, bool DV, bool Rule = true>
   __device__ static bool bregman(const Node& c, const double* feq, const double* d, double t, double& B, double* dv,
                                  const Phys& P, double zlim, bool& small) {
     constexpr int n = Lat<D>::axis(k);
@@ -400,10 +419,20 @@ template <int D> struct ShallowWater {
     double dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
     double hp = c.h + dh;
     if (!conv || fabs(dn) > 0.05 * W || !((x1 > 0.0) & (Wp > 0.0) & (hp > 0.0) & (Wp * Wp > g * hp))) {
-      dn = sw_branch_root(P0, P1, P2, P3, W, s, e1, f1, x1, c.h, g, V);
-      Wp = W + s * dn;
-      dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
-      hp = c.h + dh;
+      if constexpr (Rule) {
+        dn = sw_branch_root(P0, P1, P2, P3, W, s, e1, f1, x1, c.h, g, V);
+        Wp = W + s * dn;
+        dh = 2.0 * V * (e1 * W - s * f1 * dn) * rcp(W * Wp);
+        hp = c.h + dh;
+      } else {
+        c.rule = true;
+        B = 0.0;
+        small = false;
+        if (DV)
+#pragma unroll
+          for (int m = 0; m < M; ++m) dv[m] = 0.0;
+        return false;
+      }
     }
     small = (fabs(dh) <= zlim * c.h) & (fabs(e1) <= zlim * f1) & (fabs(dn) <= zlim * W);
     double du2 = dn * dn;
@@ -420,6 +449,16 @@ template <int D> struct ShallowWater {
     B = (g * W * dh * dh + 2.0 * s * g * hp * dh * dn + hp * Wp * du2) * (0.5 * P.inv2V);
     if (DV) dv[0] = g * dh - 0.5 * kin;
     return (x1 > 0.0) && (Wp > 0.0) && (hp > 0.0) && (Wp * Wp > g * hp) && isfinite(B);
+  }
+};
+
+template <int D> struct ShallowWaterFast : ShallowWater<D> {
+  using Base = ShallowWater<D>;
+  __device__ static bool pending(const typename Base::Node& c) { return c.rule; }
+  template <int k, bool DV>
+  __device__ static bool bregman(const typename Base::Node& c, const double* feq, const double* d, double t, double& B,
+                                 double* dv, const Phys& P, double zlim, bool& small) {
+    return Base::template bregman<k, DV, false>(c, feq, d, t, B, dv, P, zlim, small);
   }
 };
 
@@ -454,6 +493,8 @@ struct Euler2 {
   static constexpr int D = 2, M = 4, Q = 4;
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   struct Node { double rho, vel[2], p, E, irho, ip; };
+  using Fast = Euler2;  // no deferred branch (see ShallowWater::Fast)
+  __device__ static bool pending(const Node&) { return false; }
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
     const double rho = u[0], ir = rcp(rho);
     const double vx = u[1] * ir, vy = u[2] * ir;
@@ -681,8 +722,10 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
   double F1 = 0.0, dF1 = 0.0;
   bool small = true;  // all population states at t = -1 within the skip measure
   bool unused = true;
+  // S::pending: an evaluation needs the branch rule this variant leaves out
+  // (the caller relaxes the node again with it)
   if (!fsum<S>(c, feq, d, 1.0, F1, dF1, P, -1.0, unused)) {
-    fallback = true;
+    fallback = !S::pending(c);
     return 0.0;
   }
   if (!(F1 > 0.0)) return 1.0;
@@ -692,6 +735,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
   {
     double Fm = 0.0, dFm = 0.0;
     const bool okm = fsum<S>(c, feq, d, -1.0, Fm, dFm, P, S::skip_limit(c, P), small);
+    if (S::pending(c)) return 0.0;
     const double H = Fm - F1;
     if (okm && H == 0.0) return 1.0;
     if (!okm || H > 0.0) {
@@ -722,6 +766,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
         if (small) return lp;
         double F3 = 0.0, dF3 = 0.0;
         const bool ok3 = fsum<S, false>(c, feq, d, -lp, F3, dF3, P, -1.0, unused);
+        if (S::pending(c)) return 0.0;
         const double H3 = F3 - F1;
         const double xc = lp - H3 * rpd;
         if (ok3 && isfinite(xc) && fabs(xc - lp) * dmax <= tol) return xc;
@@ -740,6 +785,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
     double F = 0.0, dF = 0.0;
     bool unused = false;
     const bool ok = fsum<S>(c, feq, d, -x, F, dF, P, -1.0, unused);
+    if (S::pending(c)) return 0.0;
     const double H = F - F1, dH = -dF;
     if (ok && H == 0.0) return x;
     const bool above = !ok || (H > 0.0);
@@ -796,7 +842,8 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
   if (dmax != 0.0) {
     fallback = !adm;
     lam = 0.0;
-    if (adm) lam = entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback);
+    if (adm) lam = entropic_lambda<typename S::Fast>(c, feq, d, dmax, fsc, P, fallback);
+    if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback);
     if (fallback) {
       lam = 0.0;
       flags |= FLAG_FALLBACK;
