@@ -674,14 +674,12 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&f
   }
 }
 
-// u = sum_k f_k, f^eq(u), d = f - f^eq and the scales used by the stop rule:
-// dmax = max |d| and fsc = max |f^eq| + dmax, an upper bound of max(|f^eq|, |f|)
-// within a factor 2 (maxima of computed values need no NaN canonicalisation,
-// those of the loaded f would).
+// u = sum_k f_k, f^eq(u), d = f - f^eq and dmax = max |d| (a maximum of
+// computed values: no NaN canonicalisation, which one over the loaded f would need).
 template <class S>
 __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double (&u)[S::M],
                                            double (&feq)[S::Q][S::M], double (&d)[S::Q][S::M], double& dmax,
-                                           double& fsc, const Phys& P) {
+                                           const Phys& P) {
   constexpr int Q = S::Q, M = S::M;
 #pragma unroll
   for (int m = 0; m < M; ++m) {
@@ -692,16 +690,26 @@ __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double
   }
   Eq<S>::equilibrium(u, feq, P);
   dmax = 0.0;
-  double femax = 0.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       d[k][m] = f[k][m] - feq[k][m];
       dmax = fmax(dmax, fabs(d[k][m]));
-      femax = fmax(femax, fabs(feq[k][m]));
     }
-  fsc = femax + dmax;
+}
+
+// Tolerance of the stop rule: 2 eps (max |f^eq| + dmax), max |f^eq| + dmax being an
+// upper bound of max(|f^eq|, |f|) within a factor 2.  Only the paths past the
+// predictor shortcut need it, so it is formed there.
+template <class S>
+__device__ __forceinline__ double stop_tol(const double (&feq)[S::Q][S::M], double dmax) {
+  double femax = 0.0;
+#pragma unroll
+  for (int k = 0; k < S::Q; ++k)
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) femax = fmax(femax, fabs(feq[k][m]));
+  return 2.0 * 2.220446049250313e-16 * (femax + dmax);
 }
 
 // lambda = omega - 1 solving F(-lambda) = F(1) (eq. variableOmegaProblem in the
@@ -716,7 +724,7 @@ __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double
 // convexity domain (omega = 1 then).
 template <class S>
 __device__ inline double entropic_lambda(const typename S::Node& c, const double (&feq)[S::Q][S::M],
-                                         const double (&d)[S::Q][S::M], double dmax, double fsc, const Phys& P,
+                                         const double (&d)[S::Q][S::M], double dmax, const Phys& P,
                                          bool& fallback) {
   fallback = false;
   double F1 = 0.0, dF1 = 0.0;
@@ -729,7 +737,6 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
     return 0.0;
   }
   if (!(F1 > 0.0)) return 1.0;
-  const double tol = 2.0 * 2.220446049250313e-16 * fsc;
   double lo = 0.0, hi = INFINITY, x = 1.0;
   bool hi_bad = false;
   {
@@ -765,6 +772,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
         // close to equilibrium the prediction is within the stopping tolerance
         if (small) return lp;
         double F3 = 0.0, dF3 = 0.0;
+        const double tol = stop_tol<S>(feq, dmax);
         const bool ok3 = fsum<S, false>(c, feq, d, -lp, F3, dF3, P, -1.0, unused);
         if (S::pending(c)) return 0.0;
         const double H3 = F3 - F1;
@@ -780,6 +788,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
     }
     x = (isfinite(xn) && xn > lo && xn < hi) ? xn : (isinf(hi) ? 2.0 : 0.5 * (lo + hi));
   }
+  const double tol = stop_tol<S>(feq, dmax);
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double F = 0.0, dF = 0.0;
@@ -820,8 +829,8 @@ template <class S>
 __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
                                     double& lam_out) {
   constexpr int Q = S::Q, M = S::M;
-  double u[M], feq[Q][M], d[Q][M], dmax, fsc;
-  node_split<S>(f, u, feq, d, dmax, fsc, P);
+  double u[M], feq[Q][M], d[Q][M], dmax;
+  node_split<S>(f, u, feq, d, dmax, P);
   if (mode == 0) {
     const double om = P.omega, om1 = 1.0 - P.omega;
 #pragma unroll
@@ -842,8 +851,8 @@ __device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phy
   if (dmax != 0.0) {
     fallback = !adm;
     lam = 0.0;
-    if (adm) lam = entropic_lambda<typename S::Fast>(c, feq, d, dmax, fsc, P, fallback);
-    if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback);
+    if (adm) lam = entropic_lambda<typename S::Fast>(c, feq, d, dmax, P, fallback);
+    if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, feq, d, dmax, P, fallback);
     if (fallback) {
       lam = 0.0;
       flags |= FLAG_FALLBACK;
@@ -944,8 +953,8 @@ __device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, con
                                     double (&u)[S::M], double (&d)[S::Q][S::M], double& lam, double& om,
                                     bool& grad) {
   constexpr int Q = S::Q, M = S::M;
-  double feq[Q][M], dmax, fsc;
-  node_split<S>(h, u, feq, d, dmax, fsc, P);
+  double feq[Q][M], dmax;
+  node_split<S>(h, u, feq, d, dmax, P);
   typename S::Node c;
   const bool adm = S::prepare(u, c, P);
   om = P.omega;
@@ -957,7 +966,7 @@ __device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, con
       lam = 1.0;
     } else {
       bool fallback = !adm;
-      lam = adm ? entropic_lambda<S>(c, feq, d, dmax, fsc, P, fallback) : 0.0;
+      lam = adm ? entropic_lambda<S>(c, feq, d, dmax, P, fallback) : 0.0;
       if (fallback) {
         lam = 0.0;
         flags |= FLAG_FALLBACK;
@@ -975,8 +984,8 @@ __device__ inline void adjoint_taped(const double (&h)[S::Q][S::M], int mode, do
                                      double (&u)[S::M], double (&d)[S::Q][S::M], double& lam, double& om,
                                      bool& grad) {
   constexpr int Q = S::Q, M = S::M;
-  double feq[Q][M], dmax, fsc;
-  node_split<S>(h, u, feq, d, dmax, fsc, P);
+  double feq[Q][M], dmax;
+  node_split<S>(h, u, feq, d, dmax, P);
   om = P.omega;
   lam = P.omega - 1.0;
   grad = false;
