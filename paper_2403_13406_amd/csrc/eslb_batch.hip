@@ -7,13 +7,13 @@
 // are sorted by their step counts, longest first, so at lockstep step s the active
 // instances form a prefix and their tiles a prefix of the table.  A persistent
 // grid of blocks strides over the active tiles; the active-tile count and the step
-// counter live in device memory and are advanced by a one-thread kernel at the end
+// counter live in device memory and are advanced by a small kernel at the end
 // of each step, so one captured hipGraph of k steps replays until the longest
 // instance is done, with no host work in between.
 //
 // Offsets: transport shifts every population by the same number of cells, so an
 // instance needs one offset o (cells travelled); at pass p of lockstep step s,
-// o = o_start + s * net + cum[p].  Storage shifts follow per instance (mod nx, ny).
+// o = o_start + s * net + cum[p], kept modulo each instance's grid.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,11 +35,9 @@ namespace {
 
 struct BatchInst {
   double* f;
-  long long plane;
   int nx, ny;
-  int tiles_x;
-  int pad;
-  long long o_start;  // offset of every population when the run starts
+  int ox0, oy0;    // offset of every population when the run starts, mod nx and mod ny
+  int netx, nety;  // offset gained per composed step, mod nx and mod ny
   Phys P;
 };
 
@@ -49,53 +47,63 @@ struct BatchCtl {
   int active;         // number of such instances
 };
 
+// Offsets are kept modulo the grid: omod[i] = (o mod nx, o mod ny) of instance i at
+// the start of the current lockstep step (advanced by k_batch_advance), and
+// cmod[i * npass + p] = (c_p mod nx, c_p mod ny), c_p the cells moved by this
+// step's transports up to pass p.  A population's storage shift at pass p is then
+// one addition and one conditional subtraction (no 64-bit division per tile).
+struct TileRef {
+  int inst, tx, ty, pad;
+};
+
+// Storage byte offset of population k of cell (x, y) for offsets m = o mod (nx, ny):
+// logical f_k(x) sits at x - sign_k o along its axis.  A state is below 4 GiB
+// (checked at creation), so every access is the instance's base pointer (scalar)
+// plus a 32-bit byte offset.
 template <int D>
-__device__ __forceinline__ long long bstorage(const BatchInst& b, int k, int x, int y, int shx, int shy) {
-  const int sh = (Lat<D>::axis(k) == 0) ? (Lat<D>::sign(k) > 0 ? shx : (shx == 0 ? 0 : b.nx - shx))
-                                        : (Lat<D>::sign(k) > 0 ? shy : (shy == 0 ? 0 : b.ny - shy));
+__device__ __forceinline__ unsigned boffset(int k, int x, int y, int nx, int ny, int mx, int my) {
+  int xs = x, ys = y;
   if (Lat<D>::axis(k) == 0) {
-    int xs = x + sh;
-    if (xs >= b.nx) xs -= b.nx;
-    return (long long)y * b.nx + xs;
+    xs += (Lat<D>::sign(k) > 0) ? (mx == 0 ? 0 : nx - mx) : mx;
+    if (xs >= nx) xs -= nx;
+  } else {
+    ys += (Lat<D>::sign(k) > 0) ? (my == 0 ? 0 : ny - my) : my;
+    if (ys >= ny) ys -= ny;
   }
-  int ys = y + sh;
-  if (ys >= b.ny) ys -= b.ny;
-  return (long long)ys * b.nx + x;
+  return ((unsigned)ys * (unsigned)nx + (unsigned)xs) * 8u;
 }
 
-// One relaxation pass over every active tile.  cum: cells moved by the transports
-// of this step up to and including the one before this pass.
+__device__ __forceinline__ double& bat(double* base, unsigned byte_off) {
+  return *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
+// One relaxation pass (pass p of the step) over every active tile.
 template <class S, int D, int BX, int BY>
 __global__ __launch_bounds__(BX* BY, 2) void k_batch_stage(const BatchInst* __restrict__ inst,
-                                                          const int* __restrict__ tile_inst,
-                                                          const int* __restrict__ tile_first, const BatchCtl* ctl,
-                                                          long long net, long long cum, int mode, int omega_one,
-                                                          DevStats* st) {
+                                                          const TileRef* __restrict__ tiles, const BatchCtl* ctl,
+                                                          const int2* __restrict__ omod, const int2* __restrict__ cmod,
+                                                          int npass, int p, int mode, int omega_one, DevStats* st) {
   constexpr int Q = S::Q, M = S::M;
   const int ntiles = ctl->active_tiles;
-  const long long step = ctl->step;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int i = tile_inst[tile];
+    const TileRef tr = tiles[tile];
+    const int i = tr.inst;
     const BatchInst& b = inst[i];
-    const int lt = tile - tile_first[i];
-    const int tx = lt % b.tiles_x, ty = lt / b.tiles_x;
-    const int x = tx * BX + (int)(threadIdx.x % BX);
-    const int y = ty * BY + (int)(threadIdx.x / BX);
+    const int x = tr.tx * BX + (int)(threadIdx.x % BX);
+    const int y = tr.ty * BY + (int)(threadIdx.x / BX);
     if (x >= b.nx || y >= b.ny) continue;
-    const long long o = b.o_start + step * net + cum;
-    // storage shift of a + velocity along x is (-o) mod nx; of a - velocity, (+o) mod nx
-    long long mx = o % b.nx;
-    if (mx < 0) mx += b.nx;
-    long long my = o % b.ny;
-    if (my < 0) my += b.ny;
-    const int shx = (int)((b.nx - mx) % b.nx), shy = (int)((b.ny - my) % b.ny);
-    long long id[Q];
+    const int2 om = omod[i], cm = cmod[i * npass + p];
+    int mx = om.x + cm.x, my = om.y + cm.y;
+    if (mx >= b.nx) mx -= b.nx;
+    if (my >= b.ny) my -= b.ny;
+    const unsigned pb = (unsigned)b.nx * (unsigned)b.ny * 8u;  // plane bytes
+    unsigned off[Q];
     double f[Q][M];
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      id[k] = bstorage<D>(b, k, x, y, shx, shy);
+      off[k] = boffset<D>(k, x, y, b.nx, b.ny, mx, my);
 #pragma unroll
-      for (int m = 0; m < M; ++m) f[k][m] = b.f[(long long)(k * M + m) * b.plane + id[k]];
+      for (int m = 0; m < M; ++m) f[k][m] = bat(b.f, off[k] + (unsigned)(k * M + m) * pb);
     }
     unsigned flags = 0;
     Phys P = b.P;
@@ -107,7 +115,7 @@ __global__ __launch_bounds__(BX* BY, 2) void k_batch_stage(const BatchInst* __re
 #pragma unroll
       for (int m = 0; m < M; ++m) {
         fin &= isfinite(f[k][m]);
-        b.f[(long long)(k * M + m) * b.plane + id[k]] = f[k][m];
+        bat(b.f, off[k] + (unsigned)(k * M + m) * pb) = f[k][m];
       }
     if (!fin) flags |= FLAG_NAN;
     if (flags) {
@@ -117,21 +125,40 @@ __global__ __launch_bounds__(BX* BY, 2) void k_batch_stage(const BatchInst* __re
   }
 }
 
-// End of a lockstep step: advance the counter and shrink the active prefix.
+// End of a lockstep step: every instance's offsets move by one step (mod the
+// grid); thread 0 advances the counter and shrinks the active prefix.
 __global__ void k_batch_advance(BatchCtl* ctl, const long long* __restrict__ steps_sorted,
-                                const int* __restrict__ tiles_prefix) {
-  const long long s = ctl->step + 1;
-  int a = ctl->active;
-  while (a > 0 && steps_sorted[a - 1] <= s) --a;
-  ctl->step = s;
-  ctl->active = a;
-  ctl->active_tiles = tiles_prefix[a];
+                                const int* __restrict__ tiles_prefix, const BatchInst* __restrict__ inst,
+                                int2* __restrict__ omod, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const BatchInst& b = inst[i];
+    int2 o = omod[i];
+    o.x += b.netx;
+    if (o.x >= b.nx) o.x -= b.nx;
+    o.y += b.nety;
+    if (o.y >= b.ny) o.y -= b.ny;
+    omod[i] = o;
+  }
+  if (i == 0) {
+    const long long s = ctl->step + 1;
+    int a = ctl->active;
+    while (a > 0 && steps_sorted[a - 1] <= s) --a;
+    ctl->step = s;
+    ctl->active = a;
+    ctl->active_tiles = tiles_prefix[a];
+  }
 }
 
-__global__ void k_batch_reset(BatchCtl* ctl, int active, int tiles) {
-  ctl->step = 0;
-  ctl->active = active;
-  ctl->active_tiles = tiles;
+__global__ void k_batch_reset(BatchCtl* ctl, int active, int tiles, const BatchInst* __restrict__ inst,
+                              int2* __restrict__ omod, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) omod[i] = make_int2(inst[i].ox0, inst[i].oy0);
+  if (i == 0) {
+    ctl->step = 0;
+    ctl->active = active;
+    ctl->active_tiles = tiles;
+  }
 }
 
 struct Config {
@@ -169,11 +196,12 @@ int bhip(eslb_batch* b, hipError_t e, const char* what) {
 }
 
 template <class S, int D>
-void launch_cfg(const Config& c, int grid, hipStream_t st, const BatchInst* inst, const int* ti, const int* tf,
-                const BatchCtl* ctl, long long net, long long cum, int mode, int om1, DevStats* ds) {
-#define L(BX, BY)                                                                                               \
-  hipLaunchKernelGGL((k_batch_stage<S, D, BX, BY>), dim3(grid), dim3(BX * BY), 0, st, inst, ti, tf, ctl, net, cum, \
-                     mode, om1, ds)
+void launch_cfg(const Config& c, int grid, hipStream_t st, const BatchInst* inst, const TileRef* tiles,
+                const BatchCtl* ctl, const int2* omod, const int2* cmod, int npass, int p, int mode, int om1,
+                DevStats* ds) {
+#define L(BX, BY)                                                                                                  \
+  hipLaunchKernelGGL((k_batch_stage<S, D, BX, BY>), dim3(grid), dim3(BX * BY), 0, st, inst, tiles, ctl, omod, cmod, \
+                     npass, p, mode, om1, ds)
   if (c.bx == 64 && c.by == 4) L(64, 4);
   else if (c.bx == 128 && c.by == 2) L(128, 2);
   else if (c.bx == 256 && c.by == 1) L(256, 1);
@@ -182,9 +210,10 @@ void launch_cfg(const Config& c, int grid, hipStream_t st, const BatchInst* inst
 #undef L
 }
 
-void launch_kind(int kind, const Config& c, int grid, hipStream_t st, const BatchInst* inst, const int* ti,
-                 const int* tf, const BatchCtl* ctl, long long net, long long cum, int mode, int om1, DevStats* ds) {
-#define CALL(S, D) launch_cfg<S, D>(c, grid, st, inst, ti, tf, ctl, net, cum, mode, om1, ds)
+void launch_kind(int kind, const Config& c, int grid, hipStream_t st, const BatchInst* inst, const TileRef* tiles,
+                 const BatchCtl* ctl, const int2* omod, const int2* cmod, int npass, int p, int mode, int om1,
+                 DevStats* ds) {
+#define CALL(S, D) launch_cfg<S, D>(c, grid, st, inst, tiles, ctl, omod, cmod, npass, p, mode, om1, ds)
   ESLB_DISPATCH_KIND(kind, CALL)
 #undef CALL
 }
@@ -192,30 +221,41 @@ void launch_kind(int kind, const Config& c, int grid, hipStream_t st, const Batc
 // Device tables for one run over `order` (instance ids sorted by steps, longest first).
 struct RunTables {
   BatchInst* inst = nullptr;
-  int* tile_inst = nullptr;
-  int* tile_first = nullptr;
+  TileRef* tiles = nullptr;
   int* tiles_prefix = nullptr;
   long long* steps_sorted = nullptr;
+  int2* omod = nullptr;
+  int2* cmod = nullptr;
   BatchCtl* ctl = nullptr;
   int ntiles = 0, nact = 0;
   long long max_steps = 0;
   void release() {
     (void)hipFree(inst);
-    (void)hipFree(tile_inst);
-    (void)hipFree(tile_first);
+    (void)hipFree(tiles);
     (void)hipFree(tiles_prefix);
     (void)hipFree(steps_sorted);
+    (void)hipFree(omod);
+    (void)hipFree(cmod);
     (void)hipFree(ctl);
     *this = RunTables();
   }
 };
 
+long long pmod_ll(long long a, long long n) {
+  const long long r = a % n;
+  return r < 0 ? r + n : r;
+}
+
 int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::vector<int>& order,
                  const std::vector<long long>& steps, RunTables& T) {
   const int n = (int)order.size();
+  const eslb_ctx* c = b->proto;
+  const int npass = (int)c->passes.size();
+  const long long net = net_shift(c);
   std::vector<BatchInst> hi(n);
   std::vector<int> first(n + 1, 0), prefix(n + 1, 0);
   std::vector<long long> ss(n);
+  std::vector<int2> cm((size_t)n * npass);
   for (int r = 0; r < n; ++r) {
     const int i = order[r];
     const eslb_problem& p = b->probs[i];
@@ -223,12 +263,18 @@ int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::
     d.f = f[i];
     d.nx = p.nx;
     d.ny = p.ny;
-    d.plane = (long long)p.nx * p.ny;
-    d.tiles_x = (p.nx + cfg.bx - 1) / cfg.bx;
-    d.pad = 0;
-    d.o_start = b->offs[i];
+    d.ox0 = (int)pmod_ll(b->offs[i], p.nx);
+    d.oy0 = (int)pmod_ll(b->offs[i], p.ny);
+    d.netx = (int)pmod_ll(net, p.nx);
+    d.nety = (int)pmod_ll(net, p.ny);
     d.P = make_phys(p, b->q);
-    const int tiles = d.tiles_x * ((p.ny + cfg.by - 1) / cfg.by);
+    long long cum = 0;
+    for (int q = 0; q < npass; ++q) {
+      cum += c->passes[q].shift;
+      cm[(size_t)r * npass + q] = make_int2((int)pmod_ll(cum, p.nx), (int)pmod_ll(cum, p.ny));
+    }
+    const int tx = (p.nx + cfg.bx - 1) / cfg.bx;
+    const int tiles = tx * ((p.ny + cfg.by - 1) / cfg.by);
     first[r + 1] = first[r] + tiles;
     prefix[r + 1] = first[r + 1];
     ss[r] = steps[i];
@@ -236,9 +282,14 @@ int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::
   T.ntiles = first[n];
   T.nact = n;
   T.max_steps = n ? ss[0] : 0;
-  std::vector<int> ti((size_t)std::max(T.ntiles, 1));
-  for (int r = 0; r < n; ++r)
-    for (int t = first[r]; t < first[r + 1]; ++t) ti[t] = r;
+  std::vector<TileRef> tt((size_t)std::max(T.ntiles, 1));
+  for (int r = 0; r < n; ++r) {
+    const int tx = (hi[r].nx + cfg.bx - 1) / cfg.bx;
+    for (int t = first[r]; t < first[r + 1]; ++t) {
+      const int lt = t - first[r];
+      tt[t] = TileRef{r, lt % tx, lt / tx, 0};
+    }
+  }
   hipError_t e = hipSuccess;
   auto up = [&](void** dst, const void* src, size_t bytes) {
     if (e != hipSuccess) return;
@@ -246,10 +297,11 @@ int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::
     if (e == hipSuccess && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   up((void**)&T.inst, hi.data(), sizeof(BatchInst) * n);
-  up((void**)&T.tile_inst, ti.data(), sizeof(int) * ti.size());
-  up((void**)&T.tile_first, first.data(), sizeof(int) * first.size());
+  up((void**)&T.tiles, tt.data(), sizeof(TileRef) * tt.size());
   up((void**)&T.tiles_prefix, prefix.data(), sizeof(int) * prefix.size());
   up((void**)&T.steps_sorted, ss.data(), sizeof(long long) * n);
+  up((void**)&T.cmod, cm.data(), sizeof(int2) * cm.size());
+  if (e == hipSuccess) e = hipMalloc(&T.omod, sizeof(int2) * std::max(n, 1));
   if (e == hipSuccess) e = hipMalloc(&T.ctl, sizeof(BatchCtl));
   if (e != hipSuccess) {
     T.release();
@@ -260,20 +312,20 @@ int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::
 
 int capture_steps(eslb_batch* b, const Config& cfg, const RunTables& T, int k, hipGraphExec_t* exec) {
   eslb_ctx* c = b->proto;
-  const long long net = net_shift(c);
+  const int npass = (int)c->passes.size();
   const int grid = std::max(1, std::min(T.ntiles, b->cus * cfg.blocks_per_cu));
   hipGraph_t g = nullptr;
   int rc = bhip(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
   if (rc != ESLB_OK) return rc;
   for (int s = 0; s < k; ++s) {
-    long long cum = 0;
-    for (const Pass& p : c->passes) {
-      cum += p.shift;
-      const int mode = (p.op == PASS_PROJECT) ? 0 : c->pb.relax;
-      launch_kind(b->kind, cfg, grid, b->cap, T.inst, T.tile_inst, T.tile_first, T.ctl, net, cum, mode,
-                  p.op == PASS_PROJECT ? 1 : 0, c->st);
+    for (int p = 0; p < npass; ++p) {
+      const Pass& ps = c->passes[p];
+      const int mode = (ps.op == PASS_PROJECT) ? 0 : c->pb.relax;
+      launch_kind(b->kind, cfg, grid, b->cap, T.inst, T.tiles, T.ctl, T.omod, T.cmod, npass, p, mode,
+                  ps.op == PASS_PROJECT ? 1 : 0, c->st);
     }
-    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(1), 0, b->cap, T.ctl, T.steps_sorted, T.tiles_prefix);
+    hipLaunchKernelGGL(k_batch_advance, dim3((T.nact + 255) / 256), dim3(256), 0, b->cap, T.ctl, T.steps_sorted,
+                       T.tiles_prefix, T.inst, T.omod, T.nact);
   }
   rc = bhip(b, hipStreamEndCapture(b->cap, &g), "end capture");
   if (rc != ESLB_OK) return rc;
@@ -298,7 +350,8 @@ int run_sorted(eslb_batch* b, const Config& cfg, double* const* f, const std::ve
   if (rc == ESLB_OK) rc = bhip(b, hipEventRecord(ev, b->stream), "event record");
   if (rc == ESLB_OK) rc = bhip(b, hipStreamWaitEvent(b->cap, ev, 0), "stream wait");
   if (rc == ESLB_OK) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, b->cap, T.ctl, T.nact, T.ntiles);
+    hipLaunchKernelGGL(k_batch_reset, dim3((T.nact + 255) / 256), dim3(256), 0, b->cap, T.ctl, T.nact, T.ntiles,
+                       T.inst, T.omod, T.nact);
     rc = bhip(b, hipGetLastError(), "reset launch");
   }
   for (long long done = 0; rc == ESLB_OK && done < T.max_steps; done += k)
@@ -351,6 +404,10 @@ int eslb_batch_create(const eslb_problem* probs, int32_t n, void* stream, eslb_b
       return berr(nullptr, rc, "problem " + std::to_string(i) + ": " + why);
     }
     const eslb_problem& p = probs[i];
+    if ((long long)q * M * p.nx * p.ny * (long long)sizeof(double) >= (1ll << 32)) {
+      eslb_batch_destroy(b);
+      return berr(nullptr, ESLB_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": batch instance states must be below 4 GiB");
+    }
     if (kind != b->kind || p.relax != probs[0].relax || p.scheme != probs[0].scheme || p.kappa != probs[0].kappa) {
       eslb_batch_destroy(b);
       return berr(nullptr, ESLB_ERR_INVALID_ARG,
