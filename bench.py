@@ -1,6 +1,6 @@
 """Benchmark of the fourth-order entropy-stable LB time loop on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler2d|sw1d|burgers1d|batch|adjoint]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler2d|sw1d|burgers1d|batch|adjoint|aux]
 
 A "step" is one composed fourth-order step Phi(dt) (eq. splittingToUse): 18
 passes "shift, entropic relax" over the whole grid.  The default workload is the
@@ -27,7 +27,8 @@ One JSON line:
   riemann      (default run) schemes (A), (B), (C) of Sec. 6.3 on the 2D Euler
                four-state Riemann problem to T = 0.25 at 1024^2 and 2048^2, wall
                seconds, with the paper's own (other GPU) times beside them
---workload batch / adjoint run those two comparisons at their full sizes instead.
+--workload batch / adjoint run those two comparisons at their full sizes instead;
+--workload aux times init, moments, gather and diagnostics at the 4096^2 Euler size.
 """
 import argparse
 import json
@@ -296,6 +297,50 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
 RIEMANN_PAPER_S = {1024: {"A": 7.213, "B": 6.072, "C": 9.470}, 2048: {"A": 59.697, "B": 53.270, "C": 64.529}}
 
 
+def aux_kernels(torch, reps=20):
+    """The kernels around the stage passes at the 4096^2 Euler size: eslb_init_equilibrium (a1),
+    eslb_moments and eslb_gather (a3 observation, a2 layout), eslb_diagnostics (a7); HIP events on the
+    solver stream, algorithmic bytes per call over the mean time."""
+    from paper_2403_13406_amd import Solver
+    w = make_workload("euler2d", 0)
+    s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax=w.relax, param=w.param)
+    u0 = torch.from_numpy(w.initial_state()).cuda()
+    f = s.init_equilibrium(u0)
+    s.step(f, 1)
+    s.sync()
+    q, M, cells = s.q, s.M, w.cells
+    u = torch.empty_like(u0)
+    g = torch.empty_like(f)
+
+    def timed(fn):
+        fn()
+        s.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        for _ in range(reps):
+            fn()
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e3  # us per call
+
+    out = {}
+    for name, fn, nbytes in (
+            ("moments", lambda: s.moments(f, u), (q * M + M) * 8 * cells),
+            ("gather", lambda: s.gather(f, g), 2 * q * M * 8 * cells),
+            ("init_equilibrium", lambda: s.init_equilibrium(u0, g), (M + q * M) * 8 * cells)):
+        off = s.offsets
+        us = timed(fn)
+        s.offsets = off        # eslb_init_equilibrium starts a new state at offsets 0
+        out[name] = {"us": round(us, 2), "GB/s": round(nbytes / us / 1e3, 1),
+                     "frac_hbm": round(nbytes / us / 1e3 / HBM_PEAK_GBS, 3)}
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.diagnostics(f)       # synchronous: includes the two read-backs
+    out["diagnostics"] = {"us_synchronous": round((time.perf_counter() - t0) / reps * 1e6, 1),
+                          "bytes_read": q * M * 8 * cells}
+    return {"workload": "euler2d_%dx%d" % (w.nx, w.ny), "kernels": out}
+
+
 def riemann_compare(torch, sizes=(1024, 2048)):
     """Sec. 6.3 timing: schemes (A), (B), (C) on the 2D Euler Riemann problem to T = 0.25."""
     from paper_2403_13406_amd import Solver
@@ -353,6 +398,12 @@ def main():
                "config": {"workload": "sw2d_batch_512", "lattice": "D2Q4", "system": "shallow_water"},
                "batch": r}
         print(json.dumps(rec), flush=True)
+        return
+    if args.workload == "aux":
+        r = aux_kernels(torch)
+        print(json.dumps({"metric": "time and GB/s of the kernels around the stage passes", "n_gpus": 1,
+                          "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"]},
+                          "aux": r["kernels"]}), flush=True)
         return
     if args.workload == "adjoint":
         r = adjoint_compare(torch, 1024, 2000, 50, args.fd_dirs)

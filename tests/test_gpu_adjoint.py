@@ -172,3 +172,24 @@ def test_autograd_misfit_gradient_against_oracle_and_finite_differences():
         e = 1e-6
         fd = (loss(u0 + e * dl) - loss(u0 - e * dl)) / (2 * e)
         assert abs(fd - float(np.sum(g * dl))) <= 1e-7 * abs(fd)
+
+
+def test_adjoint_workspace_and_checkpoint_errors():
+    """Workspaces below the minimum are rejected by eslb_adjoint and eslb_adjoint_checkpointed."""
+    import ctypes
+
+    import torch
+
+    from paper_2403_13406_amd import _lib as L
+    w = small("euler2d")
+    s = solver_for(w, "entropic")
+    f0 = s.init_equilibrium(to_gpu(initial_u(w)))
+    fb = torch.zeros_like(f0)
+    need = s.adjoint_workspace_bytes(4, 2)
+    work = torch.empty(need - 8, dtype=torch.uint8, device="cuda")
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+    assert s.lib.eslb_adjoint(s.ctx, ptr(f0), 4, 2, ptr(fb), ptr(work), work.numel()) == L.ERR_INVALID_ARG
+    ckpt = torch.empty(s.checkpoint_bytes(4, 2) // 8, dtype=torch.float64, device="cuda")
+    w2 = torch.empty(need - s.checkpoint_bytes(4, 2) - 8, dtype=torch.uint8, device="cuda")
+    assert s.lib.eslb_adjoint_checkpointed(s.ctx, ptr(ckpt), 4, 2, ptr(fb), ptr(w2), w2.numel()) == L.ERR_INVALID_ARG
+    assert s.lib.eslb_step_checkpointed(s.ctx, ptr(f0), 4, 0, ptr(ckpt)) == L.ERR_INVALID_ARG

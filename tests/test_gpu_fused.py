@@ -103,3 +103,20 @@ def test_fusion_policy():
                   fused=True).step_work is not None
     assert Solver("D1Q2", "burgers", 1000, 1, V=2.0, param=(1.0,), fused=True).step_work is None  # one workgroup
     assert Solver("D2Q4", "burgers", 64, 64, V=2.0, param=(1.0, 0.5), fused=True).step_work is None
+
+
+def test_step_workspace_errors():
+    """A workspace smaller than one state and an unknown policy are rejected; detaching
+    returns eslb_step to the per-pass path."""
+    import ctypes
+
+    import torch
+
+    from paper_2403_13406_amd import _lib as L
+    from paper_2403_13406_amd import Solver
+    s = Solver("D1Q2", "burgers", 6000, 1, V=2.0, relax="fixed", param=(1.0,), fused=False)
+    small = torch.empty(100, dtype=torch.uint8, device="cuda")
+    assert s.lib.eslb_set_step_workspace(s.ctx, ctypes.c_void_p(small.data_ptr()), small.numel()) == L.ERR_INVALID_ARG
+    assert s.lib.eslb_set_fusion(s.ctx, 7) == L.ERR_INVALID_ARG
+    assert s.set_fused(True) is True and s.step_work is not None
+    assert s.set_fused(False) is False and s.step_work is None
