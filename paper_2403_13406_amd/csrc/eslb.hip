@@ -553,6 +553,124 @@ __global__ __launch_bounds__(kFusedThreads, S::kStageBlocks) void k_step_fused_1
   }
 }
 
+// A segment of fixed-omega passes of a D2Q4 problem per launch, every pass through
+// LDS: block (bx, by) owns a T x T tile and loads the window of (T + 2H)^2 cells
+// around it (H: the segment's dependency halo).  Population k of window cell (i, j)
+// sits at (i, j) - sign_k o e_axis(k) once the passes have moved it by o cells; the
+// exact index ranges of every population (one rectangle each) shrink by the shift
+// at every pass and bound the cells relaxed.  As in the 1D kernel the segment reads
+// src and writes dst.  Fixed omega only: no root search, few registers, so the
+// block can be 1024 threads at one block per CU (the window takes the LDS).
+struct Fused2Plan {
+  int npass;
+  int trailing;
+  int shift[32];
+  int op[32];
+  int T, H, W;  // owned tile side, halo, window side (LDS planes are W x W)
+};
+
+constexpr int kFused2Threads = 1024;
+
+template <class S>
+__global__ __launch_bounds__(kFused2Threads) void k_fused_2d(const double* __restrict__ src, double* __restrict__ dst,
+                                                            int nx, int ny, int4 sh_in, int4 sh_out, Phys P,
+                                                            Fused2Plan fp, DevStats* st) {
+  constexpr int Q = 4, M = S::M;
+  extern __shared__ double lds[];
+  const int T = fp.T, H = fp.H, W = fp.W, WW = fp.W * fp.W;
+  const int ax = blockIdx.x * T, ay = blockIdx.y * T;
+  const int Lx = min(T, nx - ax), Ly = min(T, ny - ay);
+  const int Wx = Lx + 2 * H, Wy = Ly + 2 * H;
+  const long long plane = (long long)nx * ny;
+  const int shi[4] = {sh_in.x, sh_in.y, sh_in.z, sh_in.w};
+  const int sho[4] = {sh_out.x, sh_out.y, sh_out.z, sh_out.w};
+  for (int idx = threadIdx.x; idx < Wx * Wy; idx += blockDim.x) {
+    const int i = idx % Wx, j = idx / Wx;
+    int x = (ax - H + i) % nx, y = (ay - H + j) % ny;
+    if (x < 0) x += nx;
+    if (y < 0) y += ny;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      int xs = x, ys = y;
+      if ((k & 1) == 0) {
+        xs += shi[k];
+        if (xs >= nx) xs -= nx;
+      } else {
+        ys += shi[k];
+        if (ys >= ny) ys -= ny;
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m) lds[(k * M + m) * WW + j * W + i] = src[(k * M + m) * plane + (long long)ys * nx + xs];
+    }
+  }
+  unsigned flags = 0;
+  int o = 0;
+  // exact ranges of the populations, each in its own window coordinates
+  int lx[4] = {0, 0, 0, 0}, hx[4] = {Wx, Wx, Wx, Wx}, ly[4] = {0, 0, 0, 0}, hy[4] = {Wy, Wy, Wy, Wy};
+  for (int p = 0; p < fp.npass; ++p) {
+    o += fp.shift[p];
+    // window offset of population k of a node: -sign_k o along its axis
+    const int dx[4] = {-o, 0, o, 0}, dy[4] = {0, -o, 0, o};
+    int rlx = lx[0] - dx[0], rhx = hx[0] - dx[0], rly = ly[0] - dy[0], rhy = hy[0] - dy[0];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      rlx = max(rlx, lx[k] - dx[k]);
+      rhx = min(rhx, hx[k] - dx[k]);
+      rly = max(rly, ly[k] - dy[k]);
+      rhy = min(rhy, hy[k] - dy[k]);
+    }
+    Phys Pp = P;
+    if (fp.op[p]) Pp.omega = 1.0;
+    const int rw = max(rhx - rlx, 0), rh = max(rhy - rly, 0);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < rw * rh; idx += blockDim.x) {
+      const int i = rlx + idx % rw, j = rly + idx / rw;
+      double f[Q][M];
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) f[k][m] = lds[(k * M + m) * WW + (j + dy[k]) * W + (i + dx[k])];
+      relax_node<S>(f, 0, Pp, flags);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          if (!isfinite(f[k][m])) flags |= FLAG_NAN;
+          lds[(k * M + m) * WW + (j + dy[k]) * W + (i + dx[k])] = f[k][m];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      lx[k] = rlx + dx[k];
+      hx[k] = rhx + dx[k];
+      ly[k] = rly + dy[k];
+      hy[k] = rhy + dy[k];
+    }
+  }
+  o += fp.trailing;
+  __syncthreads();
+  const int dx[4] = {-o, 0, o, 0}, dy[4] = {0, -o, 0, o};
+  for (int idx = threadIdx.x; idx < Lx * Ly; idx += blockDim.x) {
+    const int ti = idx % Lx, tj = idx / Lx;
+    const int i = H + ti, j = H + tj, x = ax + ti, y = ay + tj;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      int xs = x, ys = y;
+      if ((k & 1) == 0) {
+        xs += sho[k];
+        if (xs >= nx) xs -= nx;
+      } else {
+        ys += sho[k];
+        if (ys >= ny) ys -= ny;
+      }
+#pragma unroll
+      for (int m = 0; m < M; ++m)
+        dst[(k * M + m) * plane + (long long)ys * nx + xs] = lds[(k * M + m) * WW + (j + dy[k]) * W + (i + dx[k])];
+    }
+  }
+  if (flags) atomicOr(&st->flags, flags);
+}
+
 // Diagnostics, pass 1: per-block partial sums in a fixed tree order.
 // Layout of a block's partials: mass[M], micro, macro (NV = M + 2 doubles).
 constexpr int kDiagThreads = 256;
@@ -1081,9 +1199,123 @@ int fused_halo(const eslb_ctx* c) {
 // (Burgers 2^22: 6%); the entropic shallow-water pass is arithmetic-bound and its
 // fused version 4% slower (the barriers between passes), so it stays per pass.
 bool fused_active(const eslb_ctx* c) {
-  if (c->fused_L <= 0 || c->small_run || c->fuse == ESLB_FUSE_OFF) return false;
+  if (c->small_run || c->fuse == ESLB_FUSE_OFF) return false;
+  if (c->d == 2) return c->fused_W > 0 && c->pb.relax == ESLB_OMEGA_FIXED;  // D2Q4: fixed omega only
+  if (c->fused_L <= 0) return false;
   if (c->fuse == ESLB_FUSE_ALWAYS) return true;
   return c->pb.relax == ESLB_OMEGA_FIXED || c->kind != KIND_SW1;
+}
+
+// Dependency halo of a run of passes (shifts, then a trailing shift): the 1D
+// exact-range recurrence of fused_halo; in 2D it applies to each axis.
+int segment_halo(const int* shift, int n, int trailing) {
+  int o = 0, lo0 = 0, ho0 = 0, lo1 = 0, ho1 = 0;
+  for (int p = 0; p < n; ++p) {
+    o += shift[p];
+    const int rlo = std::max(lo0 + o, lo1 - o), rho = std::min(ho0 + o, ho1 - o);
+    lo0 = rlo - o;
+    ho0 = rho - o;
+    lo1 = rlo + o;
+    ho1 = rho + o;
+  }
+  o += trailing;
+  return std::max({0, lo0 + o, lo1 - o, -o - ho0, o - ho1});
+}
+
+// Fixed-omega D2Q4 steps: the passes of all nsteps steps in order (each step's
+// trailing shift folded into the next pass), cut greedily into segments whose
+// halo stays within fused_Hmax; a segment of two or more passes is one k_fused_2d
+// launch from one buffer to the other, a lone pass runs in place through k_stage.
+int run_fused_2d(eslb_ctx* c, double* f, int64_t nsteps) {
+  const int npass = (int)c->passes.size();
+  const int W = c->fused_W;
+  const size_t lds = (size_t)c->q * c->M * W * W * sizeof(double);
+  Phys P = c->phys;
+  double* buf[2] = {f, c->step_work};
+  int cur = 0, rc = ESLB_OK;
+  std::vector<int> sh, op;
+  sh.reserve(64);
+  op.reserve(64);
+  long long carry = 0;  // trailing shift of the previous step
+  auto flush = [&](int trailing) {
+    const int n = (int)sh.size();
+    if (n == 0) {
+      add_offsets(c, trailing);
+      return ESLB_OK;
+    }
+    int r = ESLB_OK;
+    // the trailing shift moves offsets only: leave it out of a segment it would widen
+    int seg_trailing = trailing;
+    if (n >= 2 && segment_halo(sh.data(), n, trailing) > c->fused_Hmax) seg_trailing = 0;
+    if (n == 1 || W - 2 * segment_halo(sh.data(), n, seg_trailing) < 8) {
+      for (int p = 0; p < n && r == ESLB_OK; ++p) {
+        add_offsets(c, sh[p]);
+        const double keep = c->phys.omega;
+        if (op[p]) c->phys.omega = 1.0;
+        r = launch_stage(c, buf[cur], 0);
+        c->phys.omega = keep;
+      }
+      add_offsets(c, trailing);
+    } else {
+      Fused2Plan fp;
+      fp.npass = n;
+      fp.trailing = seg_trailing;
+      for (int p = 0; p < n; ++p) {
+        fp.shift[p] = sh[p];
+        fp.op[p] = op[p];
+      }
+      fp.H = segment_halo(fp.shift, n, seg_trailing);
+      fp.W = W;
+      fp.T = W - 2 * fp.H;
+      const Grid gi = make_grid(c, buf[cur]);
+      long long tot = seg_trailing;
+      for (int p = 0; p < n; ++p) tot += sh[p];
+      add_offsets(c, tot);
+      const Grid go = make_grid(c, buf[1 - cur]);
+      const dim3 grid((c->pb.nx + fp.T - 1) / fp.T, (c->pb.ny + fp.T - 1) / fp.T);
+      const int4 si = make_int4(gi.sh[0], gi.sh[1], gi.sh[2], gi.sh[3]);
+      const int4 so = make_int4(go.sh[0], go.sh[1], go.sh[2], go.sh[3]);
+#define CALL(S, D) hipLaunchKernelGGL((k_fused_2d<S>), grid, dim3(kFused2Threads), lds, c->stream, buf[cur],      \
+                                      buf[1 - cur], c->pb.nx, c->pb.ny, si, so, P, fp, c->st)
+      switch (c->kind) {
+        case KIND_ADV2: CALL(Advection<2>, 2); break;
+        case KIND_BUR2: CALL(Burgers<2>, 2); break;
+        case KIND_SW2: CALL(ShallowWater<2>, 2); break;
+        case KIND_EU2: CALL(Euler2, 2); break;
+        default: break;
+      }
+#undef CALL
+      r = hip_check(c, hipGetLastError(), "fused 2D kernel launch");
+      cur = 1 - cur;
+      add_offsets(c, trailing - seg_trailing);
+    }
+    sh.clear();
+    op.clear();
+    return r;
+  };
+  for (int64_t s = 0; s < nsteps && rc == ESLB_OK; ++s) {
+    for (int p = 0; p < npass && rc == ESLB_OK; ++p) {
+      const int shift = (int)(c->passes[p].shift + (p == 0 ? carry : 0));
+      const int o = c->passes[p].op == PASS_PROJECT ? 1 : 0;
+      sh.push_back(shift);
+      op.push_back(o);
+      if ((int)sh.size() > 32 || segment_halo(sh.data(), (int)sh.size(), 0) > c->fused_Hmax) {
+        sh.pop_back();
+        op.pop_back();
+        rc = flush(0);
+        sh.push_back(shift);
+        op.push_back(o);
+      }
+    }
+    carry = c->trailing;
+  }
+  if (rc == ESLB_OK) rc = flush((int)carry);
+  if (rc == ESLB_OK && cur == 1) {
+    size_t sb = 0;
+    eslb_state_bytes(c, &sb);
+    rc = hip_check(c, hipMemcpyAsync(f, c->step_work, sb, hipMemcpyDeviceToDevice, c->stream), "device copy");
+  }
+  return rc;
 }
 
 // Composed steps of a D1Q2 problem, one fused kernel per step, alternating
@@ -1178,6 +1410,14 @@ int eslb_create(const eslb_problem* p, void* stream, eslb_ctx** out) {
   // whole run in one workgroup's LDS when the state is at most 64 KiB
   c->small_run = ((size_t)q * M * (size_t)p->nx * p->ny * sizeof(double) <= 65536) && c->passes.size() <= 32;
   // fused D1Q2 steps: windows of kFusedWindowBytes of LDS, at least 64 owned cells each
+  if (d == 2) {
+    // square windows filling the 160 KiB of LDS a block may take; segments keep
+    // (W / T)^2 <= 2, i.e. H <= 0.146 W
+    int W = (int)std::sqrt(163840.0 / (q * M * sizeof(double)));
+    while ((size_t)q * M * W * W * sizeof(double) > 163840) --W;
+    c->fused_W = W;
+    c->fused_Hmax = std::max(1, (int)(0.146 * W));
+  }
   if (d == 1 && c->passes.size() <= 32) {
     const int H = fused_halo(c);
     const int W = kFusedWindowBytes / (2 * M * (int)sizeof(double));
@@ -1267,7 +1507,8 @@ int eslb_init_equilibrium(eslb_ctx* c, const double* u, double* f) {
 int eslb_step(eslb_ctx* c, double* f, int64_t nsteps) {
   if (!c || !f || nsteps < 0) return set_err(c, ESLB_ERR_INVALID_ARG, "bad argument to eslb_step");
   if (nsteps > 0 && c->small_run && !c->track) return run_small(c, f, nsteps);
-  if (nsteps > 0 && fused_active(c) && c->step_work && !c->track) return run_fused(c, f, nsteps);
+  if (nsteps > 0 && fused_active(c) && c->step_work && !c->track)
+    return c->d == 1 ? run_fused(c, f, nsteps) : run_fused_2d(c, f, nsteps);
   for (int64_t s = 0; s < nsteps; ++s) {
     for (const Pass& ps : c->passes) {
       const int rc = run_pass(c, f, ps.shift, ps.op);
