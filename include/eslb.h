@@ -136,21 +136,23 @@ int eslb_init_equilibrium(eslb_ctx* ctx, const double* u_dev, double* f_dev);
  * 18 passes "shift, relax" with shifts kappa * (1, 2 x7, -1, -4, -1, 2 x7) and a
  * trailing shift of kappa.  Asynchronous. */
 int eslb_step(eslb_ctx* ctx, double* f_dev, int64_t nsteps);
-/* Optional workspace for eslb_step on D1Q2 problems: work_dev, a caller-owned
- * device buffer of at least eslb_state_bytes bytes that aliases no state.  With it
- * (and omega statistics off) each composed step is one fused kernel: every block
- * loads a window of cells with the step's dependency halo into LDS, runs all the
- * passes there and stores its owned cells, reading the state from one buffer and
- * writing the other (neighbouring windows overlap, so not in place); f_dev holds
- * the result on return (one copy when nsteps is odd).  Same bits as the per-pass
- * path.  work_dev = NULL detaches it; the workspace must stay allocated while
- * attached.  Other lattices ignore it. */
+/* Optional workspace for eslb_step: work_dev, a caller-owned device buffer of at
+ * least eslb_state_bytes bytes that aliases no state.  With it (and omega
+ * statistics off) eslb_step fuses passes through LDS: on D1Q2 each composed step
+ * is one kernel (a window of cells with the step's dependency halo per block); on
+ * D2Q4 with fixed omega runs of passes whose halo fits a square window are one
+ * kernel each.  A fused kernel reads the state from one buffer and writes the other
+ * (neighbouring windows overlap, so not in place); f_dev holds the result on
+ * return (one copy when the number of fused launches is odd).  Same bits as the
+ * per-pass path.  work_dev = NULL detaches it; the workspace must stay allocated
+ * while attached. */
 int eslb_set_step_workspace(eslb_ctx* ctx, void* work_dev, size_t bytes);
-/* When eslb_step takes the fused kernel (given the workspace): ESLB_FUSE_OFF
- * never; ESLB_FUSE_AUTO (default) where it is the faster path -- fixed omega, and
- * entropic omega for the scalar systems (the entropic shallow-water pass is
- * arithmetic-bound and stays per pass); ESLB_FUSE_ALWAYS for every D1Q2 problem
- * larger than the single-workgroup case.  Results are the same bits either way. */
+/* When eslb_step takes the fused kernels (given the workspace): ESLB_FUSE_OFF
+ * never; ESLB_FUSE_AUTO (default) where they are the faster path -- fixed omega,
+ * and on D1Q2 also entropic omega for the scalar systems (the entropic
+ * shallow-water and 2D passes are arithmetic-bound and stay one per launch);
+ * ESLB_FUSE_ALWAYS for every D1Q2 problem larger than the single-workgroup case
+ * (D2Q4: fixed omega only).  Results are the same bits either way. */
 enum { ESLB_FUSE_OFF = 0, ESLB_FUSE_AUTO = 1, ESLB_FUSE_ALWAYS = 2 };
 int eslb_set_fusion(eslb_ctx* ctx, int32_t policy);
 /* *yes = 1 when eslb_step takes the fused kernel under the current policy once a
