@@ -166,3 +166,25 @@ def test_fused_2d_not_taken_for_entropic_omega():
     from paper_2403_13406_amd import Solver
     assert Solver("D2Q4", "euler", 128, 128, V=3.2, relax="entropic", param=(1.4,), fused=True).step_work is None
     assert Solver("D2Q4", "euler", 128, 128, V=3.2, relax="fixed", param=(1.4,)).step_work is not None
+
+
+@pytest.mark.parametrize("lattice,system,param,V,nx,ny,kappa", [
+    ("D2Q4", "burgers", (1.0, 0.6), 2.0, 150, 90, 2), ("D2Q4", "advection", (0.3, 0.2), 1.0, 160, 75, 3),
+    ("D1Q2", "shallow_water", (9.81,), 4.5, 5000, 1, 3), ("D1Q2", "burgers", (1.0,), 2.0, 9000, 1, 2)])
+def test_fused_larger_kappa(lattice, system, param, V, nx, ny, kappa):
+    """Shifts of kappa cells per unit: longer halos (1D: 108 cells at kappa = 3), fewer passes per 2D segment
+    (the scalar systems' 71-cell windows still fuse pairs of passes); fixed omega, the same bits and offsets
+    as the per-pass path."""
+    import torch
+
+    from paper_2403_13406_amd import Solver
+    a = Solver(lattice, system, nx, ny, V=V, kappa=kappa, relax="fixed", param=param, fused=True)
+    b = Solver(lattice, system, nx, ny, V=V, kappa=kappa, relax="fixed", param=param, fused=False)
+    assert a.step_work is not None
+    u = start_state(system, nx, 44) if lattice == "D1Q2" else start_state_2d(system, nx, ny, 44)
+    fa, fb = a.init_equilibrium(to_gpu(u)), b.init_equilibrium(to_gpu(u))
+    a.step(fa, 3)
+    b.step(fb, 3)
+    assert a.sync() == 0 and b.sync() == 0
+    assert a.offsets == b.offsets
+    assert torch.equal(fa, fb)
