@@ -419,7 +419,7 @@ def main():
         torch.cuda.empty_cache()
         rec["batch"] = batch_compare(torch, 48, 0.05)
         torch.cuda.empty_cache()
-        rec["adjoint"] = adjoint_compare(torch, 1024, 100, 50)
+        rec["adjoint"] = adjoint_compare(torch, 1024, 100, 10)   # reduced: 100 steps, a 24 GiB tape
         torch.cuda.empty_cache()
         rec["riemann"] = riemann_compare(torch)
     if not args.no_cpu_baseline:

