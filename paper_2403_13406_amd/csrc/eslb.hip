@@ -1177,22 +1177,33 @@ int run_small(eslb_ctx* c, double* f, int64_t nsteps) {
   return rc;
 }
 
-// Halo of the fused D1Q2 step: the smallest H for which the owned cells of a
-// window are exact after the step (the exact-range recurrence of k_step_fused_1d,
-// which does not depend on H: ranges are kept as offsets from both window ends).
-int fused_halo(const eslb_ctx* c) {
-  int o = 0, lo0 = 0, ho0 = 0, lo1 = 0, ho1 = 0;  // [lo, Wb + ho)
-  for (const Pass& ps : c->passes) {
-    o += (int)ps.shift;
+// Dependency halo of a run of passes (shifts, then a trailing shift): the
+// smallest H for which a window of H extra cells on each side leaves its owned
+// cells exact.  The exact index ranges of the two populations of an axis are kept
+// as offsets from both window ends ([lo, W + ho), independent of W): each pass
+// relaxes the cells whose two populations are exact, and the ranges become that
+// set moved back by the populations' offsets.  In 2D it applies to each axis.
+int segment_halo(const int* shift, int n, int trailing) {
+  int o = 0, lo0 = 0, ho0 = 0, lo1 = 0, ho1 = 0;
+  for (int p = 0; p < n; ++p) {
+    o += shift[p];
     const int rlo = std::max(lo0 + o, lo1 - o), rho = std::min(ho0 + o, ho1 - o);
     lo0 = rlo - o;
     ho0 = rho - o;
     lo1 = rlo + o;
     ho1 = rho + o;
   }
-  o += c->trailing;
-  // owned cells j in [H, H + Lb) need j - o in [lo0, Wb + ho0) and j + o in [lo1, Wb + ho1)
+  o += trailing;
   return std::max({0, lo0 + o, lo1 - o, -o - ho0, o - ho1});
+}
+
+// Halo of the fused D1Q2 step: the smallest H for which the owned cells of a
+// window are exact after one composed step.
+int fused_halo(const eslb_ctx* c) {
+  int sh[32];
+  const int n = (int)c->passes.size();
+  for (int p = 0; p < n; ++p) sh[p] = (int)c->passes[p].shift;
+  return segment_halo(sh, n, c->trailing);
 }
 
 // Whether eslb_step takes the fused kernel (given a workspace).  ESLB_FUSE_AUTO:
@@ -1208,21 +1219,6 @@ bool fused_active(const eslb_ctx* c) {
   return c->pb.relax == ESLB_OMEGA_FIXED || c->kind != KIND_SW1;
 }
 
-// Dependency halo of a run of passes (shifts, then a trailing shift): the 1D
-// exact-range recurrence of fused_halo; in 2D it applies to each axis.
-int segment_halo(const int* shift, int n, int trailing) {
-  int o = 0, lo0 = 0, ho0 = 0, lo1 = 0, ho1 = 0;
-  for (int p = 0; p < n; ++p) {
-    o += shift[p];
-    const int rlo = std::max(lo0 + o, lo1 - o), rho = std::min(ho0 + o, ho1 - o);
-    lo0 = rlo - o;
-    ho0 = rho - o;
-    lo1 = rlo + o;
-    ho1 = rho + o;
-  }
-  o += trailing;
-  return std::max({0, lo0 + o, lo1 - o, -o - ho0, o - ho1});
-}
 
 // Fixed-omega D2Q4 steps: the passes of all nsteps steps in order (each step's
 // trailing shift folded into the next pass), cut greedily into segments whose
