@@ -276,7 +276,8 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
     if fd_dirs:
         rng = np.random.default_rng(w.extra["fd_seed"])
         g = x.grad
-        worst = 0.0
+        gnorm = float(torch.linalg.vector_norm(g))
+        rel, proj = [], []
         for _ in range(fd_dirs):
             dl = torch.from_numpy(rng.standard_normal(tuple(u0.shape))).cuda()
             e = 1e-6
@@ -285,10 +286,15 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
                 Lm = float(0.5 * torch.sum((time_loop(u0 - e * dl, s, nsteps) - ut) ** 2))
             fd = (Lp - Lm) / (2 * e)
             ad = float(torch.sum(g * dl))
-            worst = max(worst, abs(fd - ad) / abs(fd))
-            progress("adjoint: FD direction rel diff %.3e" % (abs(fd - ad) / abs(fd)))
+            rel.append(abs(fd - ad) / abs(fd))
+            # |g.d| / (|g| |d|): how much of the gradient the direction sees
+            proj.append(abs(ad) / (gnorm * float(torch.linalg.vector_norm(dl))))
+            progress("adjoint: FD direction rel diff %.3e (|g.d|/|g||d| = %.2e)" % (rel[-1], proj[-1]))
         rec["fd_directions"] = fd_dirs
-        rec["fd_max_rel_diff"] = worst
+        rec["fd_max_rel_diff"] = max(rel)
+        rec["fd_median_rel_diff"] = float(np.median(rel))
+        rec["fd_worst_direction_projection"] = proj[int(np.argmax(rel))]
+        rec["fd_median_projection"] = float(np.median(proj))
     return rec
 
 
