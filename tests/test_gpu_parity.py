@@ -329,3 +329,37 @@ def test_comparison_schedules(scheme, relax):
         assert max(componentwise_error(to_host(s.gather(f)), want)) <= PARITY_RTOL
         net = {4: 24, 5: 1, 6: 4}[scheme]
         assert abs(s.dt() - net * w.dx / w.V) <= 1e-15 * s.dt()
+
+
+def test_failure_injection_nan_inadmissible_subcharacteristic():
+    """Forced from the host: a NaN population, an inadmissible cell met by a relaxation pass, and V
+    below the sub-characteristic bound report their status codes (sticky until the counters reset)."""
+    from paper_2403_13406_amd import EslbError, Solver
+    from paper_2403_13406_amd import _lib as L
+    lat, sys = oracle_system("D1Q2", "shallow_water", (9.81,))
+    # NaN in one population: the pass flags it
+    s = Solver("D1Q2", "shallow_water", 64, 1, V=4.5, relax="entropic", param=(9.81,))
+    f = equilibrium(lat, sys, 4.5, np.stack([np.ones(64), np.zeros(64)])[:, None, :])
+    f[0, 0, 0, 5] = np.nan
+    fg = to_gpu(f)
+    s.relax(fg)
+    with pytest.raises(EslbError) as e:
+        s.sync()
+    assert e.value.code == L.ERR_NAN
+    # a cell whose moments are inadmissible (h < 0) reaching a relaxation
+    s2 = Solver("D1Q2", "shallow_water", 64, 1, V=4.5, relax="entropic", param=(9.81,))
+    f = equilibrium(lat, sys, 4.5, np.stack([np.ones(64), np.zeros(64)])[:, None, :])
+    f[:, 0, 0, 9] *= -1.0
+    fg = to_gpu(f)
+    s2.relax(fg)
+    with pytest.raises(EslbError) as e:
+        s2.sync()
+    assert e.value.code == L.ERR_INADMISSIBLE
+    s2.reset_counters()
+    s2.relax(to_gpu(equilibrium(lat, sys, 4.5, np.stack([np.ones(64), np.zeros(64)])[:, None, :])))
+    assert s2.sync() == 0    # the sticky status is cleared by the reset
+    # V below |u| + sqrt(g h): the initialisation warns
+    s3 = Solver("D1Q2", "shallow_water", 64, 1, V=2.0, relax="fixed", param=(9.81,))
+    with pytest.warns(RuntimeWarning):
+        s3.init_equilibrium(to_gpu(np.stack([np.ones(64), np.zeros(64)])[:, None, :]))
+        assert s3.sync() == L.WARN_SUBCHARACTERISTIC
