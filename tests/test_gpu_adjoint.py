@@ -193,3 +193,32 @@ def test_adjoint_workspace_and_checkpoint_errors():
     w2 = torch.empty(need - s.checkpoint_bytes(4, 2) - 8, dtype=torch.uint8, device="cuda")
     assert s.lib.eslb_adjoint_checkpointed(s.ctx, ptr(ckpt), 4, 2, ptr(fb), ptr(w2), w2.numel()) == L.ERR_INVALID_ARG
     assert s.lib.eslb_step_checkpointed(s.ctx, ptr(f0), 4, 0, ptr(ckpt)) == L.ERR_INVALID_ARG
+
+
+def test_adjoint_through_a_fallback_node():
+    """A node whose entropic root falls back (omega = 1) contributes no grad-omega term; the recorded
+    lambda marks it (NaN) for the adjoint passes.  Single pass (no record) and a whole step (records)
+    against the oracle's adjoint."""
+    import torch
+
+    from paper_2403_13406_amd import Solver
+    lat, sys = oracle_system("D1Q2", "burgers", (1.0,))
+    f0 = equilibrium(lat, sys, 1.0, 0.2 + 0.05 * np.sin(2 * np.pi * np.arange(16) / 16)[None, None, :])
+    f0[0, 0, 0, 3] -= 0.4
+    f0[1, 0, 0, 3] += 0.4
+    gbar = np.random.default_rng(35).standard_normal(f0.shape)
+    s = Solver("D1Q2", "burgers", 16, 1, V=1.0, relax="entropic", param=(1.0,))
+    out = to_gpu(gbar)
+    s.relax_adjoint(to_gpu(f0), out)
+    with pytest.warns(RuntimeWarning):
+        s.sync()
+    want = relax_adjoint(lat, sys, 1.0, f0, gbar, "entropic", 2.0)
+    assert max(componentwise_error(to_host(out), want)) <= ADJ_RTOL
+    s.reset_counters()
+    fb = to_gpu(gbar)
+    s.offsets = [0] * s.q
+    s.adjoint(to_gpu(f0), 1, 1, fb, tape=True)
+    with pytest.warns(RuntimeWarning):
+        s.sync()
+    want = adjoint_run(Relaxer(lat, sys, 1.0, "entropic"), f0, 1, gbar)
+    assert max(componentwise_error(to_host(fb), want)) <= 1e-9
