@@ -1212,7 +1212,10 @@ int fused_halo(const eslb_ctx* c) {
 // (Burgers 2^22: 6%); the entropic shallow-water pass is arithmetic-bound and its
 // fused version 4% slower (the barriers between passes), so it stays per pass.
 bool fused_active(const eslb_ctx* c) {
-  if (c->small_run || c->fuse == ESLB_FUSE_OFF) return false;
+  if (c->fuse == ESLB_FUSE_OFF) return false;
+  // a small D1Q2 state otherwise runs in one workgroup on one CU; windows of one
+  // cell per thread spread it over several CUs (the 1024-cell Burgers run: 3.5x)
+  if (c->small_run) return c->d == 1 && c->fused_L_small > 0 && c->pb.nx >= 2 * c->fused_L_small;
   if (c->d == 2) return c->fused_W > 0 && c->pb.relax == ESLB_OMEGA_FIXED;  // D2Q4: fixed omega only
   if (c->fused_L <= 0) return false;
   if (c->fuse == ESLB_FUSE_ALWAYS) return true;
@@ -1327,7 +1330,7 @@ int run_fused(eslb_ctx* c, double* f, int64_t nsteps) {
     fp.op[p] = c->passes[p].op == PASS_PROJECT ? 1 : 0;
   }
   fp.H = c->fused_H;
-  fp.L = c->fused_L;
+  fp.L = c->small_run ? c->fused_L_small : c->fused_L;
   const int nx = c->pb.nx;
   const unsigned nblk = (unsigned)((nx + fp.L - 1) / fp.L);
   const size_t lds = (size_t)2 * c->M * (fp.L + 2 * fp.H) * sizeof(double);
@@ -1423,6 +1426,10 @@ int eslb_create(const eslb_problem* p, void* stream, eslb_ctx** out) {
       c->fused_H = H;
       c->fused_L = W - 2 * H;
     }
+    if (kFusedThreads - 2 * H >= 32) {
+      c->fused_H = H;
+      c->fused_L_small = kFusedThreads - 2 * H;  // window of one cell per thread
+    }
   }
   c->diag_blocks = 1024;
   const int nv = M + 2;
@@ -1504,8 +1511,9 @@ int eslb_init_equilibrium(eslb_ctx* c, const double* u, double* f) {
 
 int eslb_step(eslb_ctx* c, double* f, int64_t nsteps) {
   if (!c || !f || nsteps < 0) return set_err(c, ESLB_ERR_INVALID_ARG, "bad argument to eslb_step");
-  if (nsteps > 0 && c->small_run && !c->track) return run_small(c, f, nsteps);
-  if (nsteps > 0 && fused_active(c) && c->step_work && !c->track)
+  const bool fused = fused_active(c) && c->step_work && !c->track;
+  if (nsteps > 0 && c->small_run && !c->track && !fused) return run_small(c, f, nsteps);
+  if (nsteps > 0 && fused)
     return c->d == 1 ? run_fused(c, f, nsteps) : run_fused_2d(c, f, nsteps);
   for (int64_t s = 0; s < nsteps; ++s) {
     for (const Pass& ps : c->passes) {

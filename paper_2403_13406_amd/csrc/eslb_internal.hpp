@@ -78,6 +78,7 @@ struct eslb_ctx {
   int track = 0;
   bool small_run = false;  // whole run in one workgroup's LDS (small states)
   int fused_L = 0, fused_H = 0;  // fused D1Q2 step: owned cells per block, halo (0: not available)
+  int fused_L_small = 0;         // owned cells per block for states of one workgroup (one cell per thread)
   int fuse = ESLB_FUSE_AUTO;     // eslb_set_fusion policy
   int fused_W = 0, fused_Hmax = 0;  // fused D2Q4 fixed-omega segments: window side, largest halo
   double* step_work = nullptr;   // caller-owned workspace of one state for the fused steps

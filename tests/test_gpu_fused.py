@@ -101,7 +101,8 @@ def test_fusion_policy():
     assert Solver("D1Q2", "burgers", n, 1, V=2.0, relax="fixed", param=(1.0,), fused=False).step_work is None
     assert Solver("D1Q2", "shallow_water", n, 1, V=4.5, relax="entropic", param=(9.81,),
                   fused=True).step_work is not None
-    assert Solver("D1Q2", "burgers", 1000, 1, V=2.0, param=(1.0,), fused=True).step_work is None  # one workgroup
+    assert Solver("D1Q2", "burgers", 300, 1, V=2.0, param=(1.0,), fused=True).step_work is None  # one block
+    assert Solver("D1Q2", "burgers", 1024, 1, V=2.0, param=(1.0,)).step_work is not None  # small: several CUs
     assert Solver("D2Q4", "burgers", 64, 64, V=2.0, param=(1.0, 0.5), fused=True).step_work is None
 
 
@@ -188,3 +189,26 @@ def test_fused_larger_kappa(lattice, system, param, V, nx, ny, kappa):
     assert a.sync() == 0 and b.sync() == 0
     assert a.offsets == b.offsets
     assert torch.equal(fa, fb)
+
+
+@pytest.mark.parametrize("system,param,V,n,relax", [("burgers", (1.0,), 2.0, 1024, "entropic"),
+                                                    ("shallow_water", (9.81,), 4.5, 1000, "entropic"),
+                                                    ("advection", (0.7,), 1.0, 777, "fixed")])
+def test_fused_small_states_equal_the_single_workgroup_run(system, param, V, n, relax):
+    """States of at most 64 KiB: windows of one cell per thread over several blocks give the bits of
+    the single-workgroup LDS run (and of the per-pass path); Scheme III too."""
+    import torch
+
+    from paper_2403_13406_amd import Solver
+    for scheme in (1, 3):
+        a = Solver("D1Q2", system, n, 1, V=V, relax=relax, param=param, scheme=scheme)
+        b = Solver("D1Q2", system, n, 1, V=V, relax=relax, param=param, scheme=scheme, fused=False)
+        assert a.step_work is not None and b.step_work is None
+        u = to_gpu(start_state(system, n, 45))
+        fa, fb = a.init_equilibrium(u), b.init_equilibrium(u)
+        for k in (1, 2, 17):
+            a.step(fa, k)
+            b.step(fb, k)
+            assert a.sync() == 0 and b.sync() == 0
+            assert a.offsets == b.offsets
+            assert torch.equal(fa, fb), (scheme, k)

@@ -295,7 +295,7 @@ def test_whole_run_in_lds_equals_pass_by_pass(lattice, system, nx, ny, V, param,
         u = w.initial_state()
     runs = []
     for track in (False, True):        # stats tracking forces one launch per pass
-        s = Solver(lattice, system, nx, ny, V=V, relax="entropic", scheme=scheme, param=param)
+        s = Solver(lattice, system, nx, ny, V=V, relax="entropic", scheme=scheme, param=param, fused=False)
         s.set_stats(track)
         f = s.init_equilibrium(to_gpu(u))
         s.transport(3)                 # start from unequal-to-zero offsets
