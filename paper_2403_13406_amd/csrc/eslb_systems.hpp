@@ -804,7 +804,11 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
       lo = fmax(lo, x);
     }
     const double xn = x - H / dH;
-    const bool newton_ok = ok && isfinite(xn) && (xn > lo) && (xn < hi);
+    // the bracket ends count as inside: at the root to rounding, x itself became
+    // an end (H rounds to one side) and the Newton step rounds to x; a strict test
+    // rejected that converged step and bisected the whole bracket again (up to ~45
+    // evaluations on nodes near shocks, where the predictor is not taken)
+    const bool newton_ok = ok && isfinite(xn) && (xn >= lo) && (xn <= hi);
     const double xnew = newton_ok ? xn : (isinf(hi) ? 2.0 * x : 0.5 * (lo + hi));
     if (newton_ok && fabs(xnew - x) * dmax <= tol) return xnew;
     if (!isinf(hi) && (hi - lo) * dmax <= tol) {
