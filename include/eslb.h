@@ -77,7 +77,8 @@ extern "C" {
 typedef struct eslb_problem {
   int32_t lattice;   /* ESLB_D1Q2 or ESLB_D2Q4                                   */
   int32_t system;    /* ESLB_ADVECTION .. ESLB_EULER                             */
-  int32_t nx, ny;    /* grid; ny must be 1 for D1Q2; periodic in every direction */
+  int32_t nx, ny;    /* grid; ny must be 1 for D1Q2; periodic in every direction;
+                        1 <= nx, ny <= 2^31 - 2^16 and nx * ny <= 2^40        */
   int32_t kappa;     /* >= 1                                                     */
   int32_t relax;     /* ESLB_OMEGA_FIXED or ESLB_OMEGA_ENTROPIC                  */
   int32_t scheme;    /* 1: Phi of eq. splittingToUse (Scheme I); 2, 3: Schemes II

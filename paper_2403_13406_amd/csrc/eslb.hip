@@ -32,22 +32,28 @@ namespace {
 
 // ------------------------------------------------------------------ kernels
 
+// Coordinate plus storage shift, both in [0, n): the sum is formed in 32-bit
+// unsigned arithmetic, which holds it for every extent up to 2^31 (a signed sum
+// would overflow past n = 2^30).
+__device__ __forceinline__ unsigned wrap_add(int a, int sh, int n) {
+  unsigned s = (unsigned)a + (unsigned)sh;
+  if (s >= (unsigned)n) s -= (unsigned)n;
+  return s;
+}
+
 template <int D>
 __device__ __forceinline__ long long storage_index(const Grid& g, int k, int x, int y) {
-  if (Lat<D>::axis(k) == 0) {
-    int xs = x + g.sh[k];
-    if (xs >= g.nx) xs -= g.nx;
-    return (long long)y * g.nx + xs;
-  }
-  int ys = y + g.sh[k];
-  if (ys >= g.ny) ys -= g.ny;
-  return (long long)ys * g.nx + x;
+  if (Lat<D>::axis(k) == 0) return (long long)y * g.nx + wrap_add(x, g.sh[k], g.nx);
+  return (long long)wrap_add(y, g.sh[k], g.ny) * g.nx + x;
 }
 
 // Planes of at most 2^29 nodes: byte offsets within a plane fit 32 bits, and
 // with the plane base wave-uniform the accesses take the scalar-base +
 // 32-bit-offset form (no per-lane 64-bit address arithmetic).
 constexpr long long kPlane32 = 1ll << 29;
+
+// Largest grid extent per axis.
+constexpr int kMaxExtent = (int)((1ll << 31) - (1ll << 16));
 
 template <int D>
 __device__ __forceinline__ unsigned storage_offset32(const Grid& g, int k, int x, int y) {
@@ -490,9 +496,7 @@ __global__ __launch_bounds__(kFusedThreads, S::kStageBlocks) void k_step_fused_1
   for (int j = threadIdx.x; j < Wb; j += blockDim.x) {
     long long x = (a - H + j) % nx;
     if (x < 0) x += nx;
-    int s0 = (int)x + sh_in0, s1 = (int)x + sh_in1;
-    if (s0 >= nx) s0 -= nx;
-    if (s1 >= nx) s1 -= nx;
+    const unsigned s0 = wrap_add((int)x, sh_in0, nx), s1 = wrap_add((int)x, sh_in1, nx);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       lds[m * W + j] = src[(long long)m * nx + s0];
@@ -540,9 +544,7 @@ __global__ __launch_bounds__(kFusedThreads, S::kStageBlocks) void k_step_fused_1
   __syncthreads();
   for (int t = threadIdx.x; t < Lb; t += blockDim.x) {
     const int x = (int)a + t, j = H + t;
-    int s0 = x + sh_out0, s1 = x + sh_out1;
-    if (s0 >= nx) s0 -= nx;
-    if (s1 >= nx) s1 -= nx;
+    const unsigned s0 = wrap_add(x, sh_out0, nx), s1 = wrap_add(x, sh_out1, nx);
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       dst[(long long)m * nx + s0] = lds[m * W + j - o];
@@ -593,14 +595,8 @@ __global__ __launch_bounds__(kFused2Threads) void k_fused_2d(const double* __res
     if (y < 0) y += ny;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      int xs = x, ys = y;
-      if ((k & 1) == 0) {
-        xs += shi[k];
-        if (xs >= nx) xs -= nx;
-      } else {
-        ys += shi[k];
-        if (ys >= ny) ys -= ny;
-      }
+      const unsigned xs = (k & 1) == 0 ? wrap_add(x, shi[k], nx) : (unsigned)x;
+      const unsigned ys = (k & 1) == 0 ? (unsigned)y : wrap_add(y, shi[k], ny);
 #pragma unroll
       for (int m = 0; m < M; ++m) lds[(k * M + m) * WW + j * W + i] = src[(k * M + m) * plane + (long long)ys * nx + xs];
     }
@@ -657,14 +653,8 @@ __global__ __launch_bounds__(kFused2Threads) void k_fused_2d(const double* __res
     const int i = H + ti, j = H + tj, x = ax + ti, y = ay + tj;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      int xs = x, ys = y;
-      if ((k & 1) == 0) {
-        xs += sho[k];
-        if (xs >= nx) xs -= nx;
-      } else {
-        ys += sho[k];
-        if (ys >= ny) ys -= ny;
-      }
+      const unsigned xs = (k & 1) == 0 ? wrap_add(x, sho[k], nx) : (unsigned)x;
+      const unsigned ys = (k & 1) == 0 ? (unsigned)y : wrap_add(y, sho[k], ny);
 #pragma unroll
       for (int m = 0; m < M; ++m)
         dst[(k * M + m) * plane + (long long)ys * nx + xs] = lds[(k * M + m) * WW + (j + dy[k]) * W + (i + dx[k])];
@@ -821,12 +811,12 @@ Grid make_grid(const eslb_ctx* c, double* f) {
 void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   if (c->d == 1) {
     block = dim3(256, 1, 1);
-    grid = dim3((c->pb.nx + 255) / 256, 1, 1);
+    grid = dim3((unsigned)(((long long)c->pb.nx + 255) / 256), 1, 1);
   } else {
     const int bx = c->pb.nx >= 64 ? 64 : 32;
     const int by = 256 / bx;
     block = dim3(bx, by, 1);
-    grid = dim3((c->pb.nx + bx - 1) / bx, (c->pb.ny + by - 1) / by, 1);
+    grid = dim3((unsigned)(((long long)c->pb.nx + bx - 1) / bx), (unsigned)(((long long)c->pb.ny + by - 1) / by), 1);
   }
 }
 
@@ -900,6 +890,9 @@ int validate_problem(const eslb_problem* p, std::string& why, int* kind, int* d,
   if (p->nx < 1 || p->ny < 1) { why = "nx and ny must be >= 1"; return ESLB_ERR_INVALID_ARG; }
   if (p->lattice == ESLB_D1Q2 && p->ny != 1) { why = "D1Q2 needs ny == 1"; return ESLB_ERR_INVALID_ARG; }
   if ((long long)p->nx * p->ny > (1ll << 40)) { why = "grid too large"; return ESLB_ERR_INVALID_ARG; }
+  // kernels form node coordinates as int from rounded-up grids (up to 1023
+  // threads past the extent)
+  if (p->nx > kMaxExtent || p->ny > kMaxExtent) { why = "nx and ny must be <= 2^31 - 2^16"; return ESLB_ERR_INVALID_ARG; }
   if (p->kappa < 1) { why = "kappa must be >= 1"; return ESLB_ERR_INVALID_ARG; }
   if (!(p->V > 0.0) || !std::isfinite(p->V)) { why = "V must be > 0"; return ESLB_ERR_INVALID_ARG; }
   if (!(p->dx > 0.0) || !std::isfinite(p->dx)) { why = "dx must be > 0"; return ESLB_ERR_INVALID_ARG; }
@@ -1273,7 +1266,8 @@ int run_fused_2d(eslb_ctx* c, double* f, int64_t nsteps) {
       for (int p = 0; p < n; ++p) tot += sh[p];
       add_offsets(c, tot);
       const Grid go = make_grid(c, buf[1 - cur]);
-      const dim3 grid((c->pb.nx + fp.T - 1) / fp.T, (c->pb.ny + fp.T - 1) / fp.T);
+      const dim3 grid((unsigned)(((long long)c->pb.nx + fp.T - 1) / fp.T),
+                      (unsigned)(((long long)c->pb.ny + fp.T - 1) / fp.T));
       const int4 si = make_int4(gi.sh[0], gi.sh[1], gi.sh[2], gi.sh[3]);
       const int4 so = make_int4(go.sh[0], go.sh[1], go.sh[2], go.sh[3]);
 #define CALL(S, D) hipLaunchKernelGGL((k_fused_2d<S>), grid, dim3(kFused2Threads), lds, c->stream, buf[cur],      \
@@ -1332,7 +1326,7 @@ int run_fused(eslb_ctx* c, double* f, int64_t nsteps) {
   fp.H = c->fused_H;
   fp.L = c->small_run ? c->fused_L_small : c->fused_L;
   const int nx = c->pb.nx;
-  const unsigned nblk = (unsigned)((nx + fp.L - 1) / fp.L);
+  const unsigned nblk = (unsigned)(((long long)nx + fp.L - 1) / fp.L);
   const size_t lds = (size_t)2 * c->M * (fp.L + 2 * fp.H) * sizeof(double);
   const long long net = net_shift(c);
   Phys P = c->phys;
