@@ -1,0 +1,105 @@
+"""Degenerate calls and grids: zero steps, grids of one to three cells per axis (every shift
+wraps the period, often several times), and the zero-step adjoint.
+
+Bar as in the other parity tests: states within 1e-12 of the oracle per conserved component;
+identities bit for bit.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import PARITY_RTOL, componentwise_error, oracle_system, to_gpu, to_host
+from oracle.scheme import Relaxer, run
+from oracle.systems import equilibrium
+from paper_2403_13406_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BASE = {  # lattice, system -> (V, param, base state u, relative spread of u)
+    ("D1Q2", "burgers"): (2.0, (1.0,), [0.3], 0.1),
+    ("D1Q2", "shallow_water"): (4.5, (9.81,), [1.0, 0.1], 0.05),
+    ("D2Q4", "burgers"): (2.0, (1.0, 0.6), [0.3], 0.1),
+    ("D2Q4", "advection"): (1.0, (0.2, -0.15), [0.5], 0.2),
+    ("D2Q4", "shallow_water"): (8.0, (9.81,), [1.0, 0.1, -0.05], 0.05),
+    ("D2Q4", "euler"): (3.2, (1.4,), [1.0, 0.05, -0.03, 2.5], 0.05),
+}
+
+
+def tiny_state(lattice, system, nx, ny, seed):
+    """Logical populations f^eq(u) + delta, sum_k delta_k = 0 (u kept), |delta| ~ 1e-3 |f|."""
+    V, param, base, spread = BASE[(lattice, system)]
+    lat, sys = oracle_system(lattice, system, param)
+    rng = np.random.default_rng(seed)
+    u = np.array(base)[:, None, None] * (1.0 + spread * rng.uniform(-1.0, 1.0, size=(len(base), ny, nx)))
+    f = equilibrium(lat, sys, V, u)
+    r = rng.uniform(-1.0, 1.0, size=f.shape)
+    delta = 1e-3 * np.max(np.abs(f), axis=(0, 2, 3), keepdims=True) * (r - r.mean(axis=0, keepdims=True))
+    return lat, sys, V, param, f + delta
+
+
+@pytest.mark.parametrize("lattice,system,nx,ny", [
+    ("D1Q2", "burgers", 1, 1), ("D1Q2", "burgers", 3, 1), ("D1Q2", "shallow_water", 1, 1),
+    ("D1Q2", "shallow_water", 2, 1), ("D2Q4", "euler", 1, 1), ("D2Q4", "euler", 3, 2),
+    ("D2Q4", "shallow_water", 1, 3), ("D2Q4", "burgers", 2, 1), ("D2Q4", "advection", 3, 3),
+])
+@pytest.mark.parametrize("per_pass", [False, True])
+def test_grids_of_one_to_three_cells(lattice, system, nx, ny, per_pass):
+    """Three entropic composed steps on grids smaller than one transport (shift -4 wraps a 3-cell
+    period more than once); per_pass: one launch per pass (omega tracking on) instead of the
+    whole run in one workgroup."""
+    from paper_2403_13406_amd import Solver
+    lat, sys, V, param, f0 = tiny_state(lattice, system, nx, ny, seed=nx * 7 + ny)
+    s = Solver(lattice, system, nx, ny, V=V, relax="entropic", param=param)
+    if per_pass:
+        s.set_stats(True)
+    f = to_gpu(f0)
+    s.step(f, 3)
+    assert s.sync() == 0
+    got = to_host(s.gather(f))
+    want = run(Relaxer(lat, sys, V, "entropic"), f0, 3)
+    assert max(componentwise_error(got, want)) <= PARITY_RTOL
+    assert s.offsets == [72] * lat.q
+
+
+@pytest.mark.parametrize("lattice,system,nx,ny,relax,fused", [
+    ("D2Q4", "euler", 70, 37, "entropic", "auto"),
+    ("D1Q2", "burgers", 6000, 1, "entropic", True),       # fused whole-step kernel
+    ("D1Q2", "burgers", 1024, 1, "entropic", "auto"),     # fused, small-state variant
+    ("D1Q2", "shallow_water", 300, 1, "entropic", "auto"),  # whole run in one workgroup
+    ("D2Q4", "advection", 40, 33, "fixed", True),         # fused fixed-omega segments
+])
+def test_zero_steps_leave_state_and_offsets(lattice, system, nx, ny, relax, fused):
+    """eslb_step with nsteps = 0 is the identity on every path; a negative count is an error."""
+    import torch
+
+    from paper_2403_13406_amd import EslbError, Solver
+    lat, sys, V, param, f0 = tiny_state(lattice, system, nx, ny, seed=3)
+    s = Solver(lattice, system, nx, ny, V=V, relax=relax, param=param, fused=fused)
+    offs = [3, -5, 7, 11][:lat.q]
+    s.offsets = offs
+    f = to_gpu(f0)
+    ref = f.clone()
+    s.step(f, 0)
+    assert s.sync() == 0
+    assert torch.equal(f, ref)
+    assert s.offsets == offs
+    with pytest.raises(EslbError):
+        s.step(f, -1)
+    assert torch.equal(f, ref)
+
+
+def test_adjoint_of_zero_steps_is_identity():
+    """eslb_adjoint over 0 steps hands the cotangent back unchanged (bitwise)."""
+    import torch
+
+    from paper_2403_13406_amd import Solver
+    w = W.euler2d(16, ny=12, nsteps=1)
+    s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
+    f0 = s.init_equilibrium(to_gpu(w.initial_state()))
+    s.offsets = [2, -3, 5, 1]
+    rng = np.random.default_rng(4)
+    fbar = to_gpu(rng.standard_normal(s.state_shape))
+    ref = fbar.clone()
+    s.adjoint(f0, 0, 1, fbar)
+    assert s.sync() == 0
+    assert torch.equal(fbar, ref)
+    assert s.offsets == [2, -3, 5, 1]
