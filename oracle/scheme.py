@@ -20,8 +20,6 @@ R_1 after every psi.  The standard second-order lattice Boltzmann scheme is
 R T(Delta t) (Sec. 2.1.3); the fair comparison of Sec. 3.1 advances Delta t
 with (R T(Delta t / 24))^24.
 """
-import numpy as np
-
 from .lattice import transport
 from .relaxation import relax_entropic, relax_fixed
 

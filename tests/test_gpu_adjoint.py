@@ -14,7 +14,7 @@ import pytest
 
 from gpu_common import componentwise_error, off_equilibrium, oracle_system, to_gpu, to_host
 from oracle.adjoint import adjoint_run, misfit_gradient, relax_adjoint
-from oracle.scheme import Relaxer, run
+from oracle.scheme import Relaxer
 from oracle.systems import equilibrium
 from paper_2403_13406_amd import workloads as W
 from test_gpu_parity import initial_u, small, solver_for
