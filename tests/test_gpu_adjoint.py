@@ -62,6 +62,32 @@ def test_adjoint_through_steps(name, nsteps, ck):
         assert l2 <= MULTI_STEP_L2, (m, l2)
 
 
+def test_full_size_adjoint_sampled():
+    """The Euler 1024^2 adjoint workload in the benchmark's configuration (checkpoint every 50, taped
+    workspace), one step: sampled cotangents of f0 against the oracle's reverse sweep on a 161 x 161
+    periodic window around each node (the cotangent at a node depends on the final cotangent within
+    36 cells and on f0 within 72, so the window centre is exact); one window straddles the wrap."""
+    w = W.euler2d_adjoint()
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    u = w.initial_state()
+    s = solver_for(w, "entropic")
+    f0 = s.init_equilibrium(to_gpu(u))
+    fbarT = np.random.default_rng(33).standard_normal(f0.shape)
+    fb = to_gpu(fbarT)
+    s.adjoint(f0, 1, w.extra["ckpt_every"], fb, tape=True)
+    assert s.sync() == 0
+    got = to_host(fb)
+    R = 80
+    for cy, cx in [(3, 1020), (517, 290)]:
+        ys = (np.arange(-R, R + 1) + cy) % w.ny
+        xs = (np.arange(-R, R + 1) + cx) % w.nx
+        fw = fbarT[:, :, ys][:, :, :, xs]
+        want = adjoint_run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u[:, ys][:, :, xs]), 1, fw)
+        for m in range(want.shape[1]):
+            scale = np.max(np.abs(want[:, m]))
+            assert np.max(np.abs(got[:, m, cy, cx] - want[:, m, R, R])) <= 1e-9 * scale
+
+
 def test_checkpoint_interval_does_not_change_the_result():
     """Recomputation is deterministic, so any checkpoint interval gives the same bits."""
     w = small("euler2d")
