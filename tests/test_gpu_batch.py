@@ -86,3 +86,44 @@ def test_autotune_leaves_states_untouched_and_picks_a_config():
     for f, g in zip(states, before):
         assert np.array_equal(to_host(f), g)
     assert all(b.offsets(i) == [0] * 4 for i in range(len(ws)))
+
+
+def test_batch_at_the_ensemble_sizes():
+    """The first eight instances of the 512-instance ensemble (64^2 .. 1024^2 grids, their own initial
+    data), one to three steps each so the active set shrinks during the run, autotuned as in the
+    benchmark: bitwise equal to per-instance runs; the 1024^2 instance also sampled against the
+    oracle on 81 x 81 periodic windows (one step moves a population by at most 36 cells)."""
+    from paper_2403_13406_amd import Batch, Solver
+    ws = W.sw2d_batch(8)
+    steps = [3, 1, 2, 3, 1, 2, 3, 1]
+    assert (ws[1].nx, ws[1].ny) == (1024, 1024)
+    b = Batch([problem_kw(w) for w in ws])
+    states, plain, u0 = [], [], []
+    for w, n in zip(ws, steps):
+        s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
+        u = w.initial_state()
+        u0.append(u)
+        f = s.init_equilibrium(to_gpu(u))
+        states.append(f.clone())
+        s.step(f, n)
+        assert s.sync() == 0
+        plain.append((to_host(f), s.offsets))
+    b.autotune(states, trial_steps=1)
+    b.run(states, steps)
+    assert b.sync() == 0
+    for i in range(len(ws)):
+        assert b.offsets(i) == plain[i][1]
+        assert np.array_equal(to_host(states[i]), plain[i][0]), i
+    w = ws[1]
+    lat, sys = oracle_system(w.lattice, w.system, w.param)
+    s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
+    s.offsets = b.offsets(1)
+    g = to_host(s.gather(states[1]))
+    R = 40
+    for cy, cx in [(0, 1023), (600, 77)]:
+        ys = (np.arange(-R, R + 1) + cy) % w.ny
+        xs = (np.arange(-R, R + 1) + cx) % w.nx
+        fw = run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u0[1][:, ys][:, :, xs]), 1)
+        for m in range(fw.shape[1]):
+            scale = np.max(np.abs(fw[:, m]))
+            assert np.max(np.abs(g[:, m, cy, cx] - fw[:, m, R, R])) <= PARITY_RTOL * scale
