@@ -279,7 +279,8 @@ int eslb_batch_set_offsets(eslb_batch* batch, int32_t i, const int64_t* offsets)
 /* Synchronise and return the sticky status of the whole batch. */
 int eslb_batch_sync_status(eslb_batch* batch);
 /* Launch configuration: tile block_x x block_y (64x4, 64x2, 128x2, 256x1, 32x8),
- * persistent blocks per compute unit, composed steps per captured graph. */
+ * persistent blocks per compute unit (0: one block per tile, dispatched by the
+ * hardware), composed steps per captured graph. */
 int eslb_batch_set_config(eslb_batch* batch, int32_t block_x, int32_t block_y, int32_t blocks_per_cu,
                           int32_t steps_per_graph);
 int eslb_batch_get_config(const eslb_batch* batch, int32_t* cfg4);

@@ -161,11 +161,16 @@ __global__ void k_batch_reset(BatchCtl* ctl, int active, int tiles, const BatchI
   }
 }
 
+// blocks_per_cu = 0: one block per tile of the whole table (the blocks past the
+// active prefix return at once), so the hardware dispatcher balances the tiles
+// whose root searches take longer; otherwise a persistent grid of that many
+// blocks per CU strides over the tiles.
 struct Config {
   int bx, by, blocks_per_cu;
 };
 
-const Config kConfigs[] = {{64, 4, 8}, {64, 4, 4}, {64, 4, 16}, {128, 2, 8}, {256, 1, 8}, {32, 8, 8}, {64, 2, 8}};
+const Config kConfigs[] = {{64, 4, 8}, {64, 4, 4}, {64, 4, 16}, {128, 2, 8}, {256, 1, 8},
+                           {32, 8, 8}, {64, 2, 8}, {64, 4, 0}, {64, 2, 0}};
 
 }  // namespace
 
@@ -313,7 +318,7 @@ int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::
 int capture_steps(eslb_batch* b, const Config& cfg, const RunTables& T, int k, hipGraphExec_t* exec) {
   eslb_ctx* c = b->proto;
   const int npass = (int)c->passes.size();
-  const int grid = std::max(1, std::min(T.ntiles, b->cus * cfg.blocks_per_cu));
+  const int grid = std::max(1, cfg.blocks_per_cu > 0 ? std::min(T.ntiles, b->cus * cfg.blocks_per_cu) : T.ntiles);
   hipGraph_t g = nullptr;
   int rc = bhip(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
   if (rc != ESLB_OK) return rc;
@@ -477,7 +482,7 @@ int eslb_batch_set_config(eslb_batch* b, int32_t block_x, int32_t block_y, int32
   if (!b) return ESLB_ERR_INVALID_ARG;
   for (const Config& c : kConfigs) {
     if (c.bx == block_x && c.by == block_y) {
-      if (blocks_per_cu < 1 || steps_per_graph < 1) break;
+      if (blocks_per_cu < 0 || steps_per_graph < 1) break;
       b->cfg = Config{block_x, block_y, blocks_per_cu};
       b->steps_per_graph = steps_per_graph;
       return ESLB_OK;

@@ -26,7 +26,7 @@ def problem_kw(w):
     return dict(lattice=w.lattice, system=w.system, nx=w.nx, ny=w.ny, V=w.V, relax="entropic", param=w.param)
 
 
-@pytest.mark.parametrize("config", [None, (64, 4, 2, 3), (256, 1, 8, 1), (32, 8, 4, 5)])
+@pytest.mark.parametrize("config", [None, (64, 4, 2, 3), (256, 1, 8, 1), (32, 8, 4, 5), (64, 2, 0, 2)])
 def test_batch_equals_per_instance_runs_bitwise(config):
     from paper_2403_13406_amd import Batch, Solver
     ws = ensemble(9, [13, 64, 70, 128], (1, 6))
