@@ -391,23 +391,25 @@ template <int D> struct ShallowWater {
     const double P1 = gV * a * (b + cq) + W2 * W * (2.0 * s * gn - x1 * W);
     const double P2 = gV * a * a + W2 * (gn - 2.0 * s * x1 * W);
     const double P3 = -x1 * W2;
-    // start from the second-order series reversion of the root about dn = 0,
-    // -P0/P1 - P2 P0^2/P1^3 (error O(dn^3)), while its correction is a small change
-    // of the first Newton iterate from 0 (|P2 d0 / P1| <= 1/4); otherwise from that
-    // iterate itself.  Then Newton.
+    // start from the third-order series reversion of the root about dn = 0,
+    // d0 (1 - q + 2 q^2 - r) with d0 = -P0/P1, q = P2 d0 / P1, r = P3 d0^2 / P1
+    // (error O(dn^4)), while its corrections are small changes of the first Newton
+    // iterate from 0 (|q|, |r| <= 1/4); otherwise from that iterate itself.  Then
+    // Newton, stopped once the error its recurrence leaves after a step,
+    // |P''/(2P')| st^2, is below 2^-53 |dn|: near the cell state one step.
     const double rP1 = rcp(P1);
     const double d0 = -P0 * rP1;
-    const double q = P2 * d0 * rP1;
-    double dn = fabs(q) <= 0.25 ? d0 * (1.0 - q) : d0;
+    const double q = P2 * d0 * rP1, r = P3 * d0 * d0 * rP1;
+    double dn = (fabs(q) <= 0.25 && fabs(r) <= 0.25) ? d0 * (1.0 - q + (2.0 * q * q - r)) : d0;
     bool conv = false;
 #pragma unroll 1
     for (int it = 0; it < 12; ++it) {
       const double Pv = P0 + dn * (P1 + dn * (P2 + dn * P3));
       const double dP = P1 + dn * (2.0 * P2 + 3.0 * P3 * dn);
-      const double st = Pv * rcp(dP);
+      const double rdP = rcp(dP);
+      const double st = Pv * rdP;
       dn -= st;
-      // quadratic convergence: once a step is below 2^-40 |dn| the error left is ~2^-80 |dn|
-      if (!(fabs(st) > 0x1p-40 * fabs(dn))) {
+      if (!(fabs(P2 + 3.0 * P3 * dn) * fabs(rdP) * st * st > 0x1p-53 * fabs(dn))) {
         conv = true;
         break;
       }
@@ -830,7 +832,7 @@ enum : unsigned { FLAG_INADMISSIBLE = 1u, FLAG_NAN = 2u, FLAG_FALLBACK = 4u, FLA
 // lam_out = the lambda = omega - 1 of the update, NaN where the root search fell
 // back to omega = 1 (the adjoint then drops the grad-omega term).
 template <class S>
-__device__ inline double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
+__device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
                                     double& lam_out) {
   constexpr int Q = S::Q, M = S::M;
   double u[M], feq[Q][M], d[Q][M], dmax;
