@@ -21,7 +21,8 @@ One JSON line:
                sources still match
   cpu_baseline the CPU oracle, single-threaded, on a bounded sample of the workload
   batch        (default run) a reduced sample of the batched ensemble: one
-               persistent-kernel batch run vs the plain per-instance loop, same GPU
+               batch run (one stage kernel per pass over all instances) vs the plain
+               per-instance loop, same GPU
   adjoint      (default run) forward vs forward+adjoint with checkpointing on the
                1024^2 Euler grid, same GPU
   riemann      (default run) schemes (A), (B), (C) of Sec. 6.3 on the 2D Euler
@@ -189,7 +190,7 @@ def progress(msg):
 
 
 def batch_compare(torch, count, steps_scale, tune=True, seed_base=0):
-    """Batched ensemble (one persistent kernel) vs the plain per-instance loop, same GPU."""
+    """Batched ensemble (one stage kernel per pass over all instances) vs the plain per-instance loop, same GPU."""
 
     from paper_2403_13406_amd import Batch, Solver
     from paper_2403_13406_amd import workloads as W

@@ -256,7 +256,8 @@ int eslb_adjoint_checkpointed(eslb_ctx* ctx, const double* ckpt_dev, int64_t nst
 /* ---------------------------------------------------------------- batched ensembles
  * Many independent problems of one kind (same lattice, system, relax mode, scheme
  * and kappa; grid sizes, V, dx and system parameters may differ) advanced by one
- * persistent stage kernel over a device table of tiles of every active instance,
+ * stage kernel per pass over a device table of tiles of every active instance
+ * (a persistent grid, or one block per tile: the launch configuration),
  * all instances in lockstep through the same composed-step schedule; the passes
  * of a few steps are captured in one hipGraph whose replays need no host work.
  * Not a method of the paper: an execution pattern for many problems at once; each

@@ -6,7 +6,7 @@ from .solver import EslbError, make_problem
 
 
 class Batch:
-    """Independent problems of one kind advanced in lockstep by one persistent kernel."""
+    """Independent problems of one kind advanced in lockstep, one stage kernel per pass over all of them."""
 
     def __init__(self, problems, stream=None):
         """problems: list of dicts of make_problem keyword arguments (same lattice/system/relax)."""
