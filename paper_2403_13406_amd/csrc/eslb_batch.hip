@@ -1,12 +1,14 @@
 // Batched ensembles: many independent problems of one (lattice, system) kind and
-// uneven grid sizes advanced together by one persistent stage kernel.
+// uneven grid sizes advanced together, one stage kernel per pass over all of them.
 //
 // Every instance runs the same composed-step schedule (eq. splittingToUse), so
 // the ensemble advances in lockstep, pass by pass.  The grid of every instance is
 // cut into tiles of one block; a device table maps tile -> instance.  Instances
 // are sorted by their step counts, longest first, so at lockstep step s the active
-// instances form a prefix and their tiles a prefix of the table.  A persistent
-// grid of blocks strides over the active tiles; the active-tile count and the step
+// instances form a prefix and their tiles a prefix of the table.  The stage
+// kernel covers the active tiles, either with a persistent grid of blocks that
+// strides over them or with one block per tile of the whole table (the launch
+// configuration, chosen by the autotuner); the active-tile count and the step
 // counter live in device memory and are advanced by a small kernel at the end
 // of each step, so one captured hipGraph of k steps replays until the longest
 // instance is done, with no host work in between.

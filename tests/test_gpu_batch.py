@@ -1,4 +1,4 @@
-"""Batched ensemble (one persistent kernel, hipGraph-captured steps) against the plain
+"""Batched ensemble (one stage kernel per pass over all instances, hipGraph-captured steps) against the plain
 per-instance path and the oracle."""
 import numpy as np
 import pytest
