@@ -820,6 +820,18 @@ void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   }
 }
 
+// The stage kernel on D2Q4 grids: 64 x 2 blocks (two waves, each one 64-node row
+// segment).  Its waves run for very different times (root searches), and a
+// smaller block frees its CU slots sooner: 1% faster than 64 x 4 on the 4096^2
+// Euler and SW2D passes; D1Q2 keeps 256 threads (smaller blocks measured slower).
+void stage_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
+  launch_shape(c, grid, block);
+  if (c->d == 2 && c->pb.nx >= 64) {
+    block = dim3(64, 2, 1);
+    grid = dim3(grid.x, (unsigned)(((long long)c->pb.ny + 1) / 2), 1);
+  }
+}
+
 #define ESLB_DISPATCH(KIND, CALL) ESLB_DISPATCH_KIND(KIND, CALL)
 
 // rec (optional): q*M planes that receive the pass input, and lamr (optional
@@ -827,7 +839,7 @@ void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
 int launch_stage(eslb_ctx* c, double* f, int mode, double* rec, double* lamr) {
   const Grid g = make_grid(c, f);
   dim3 grid, block;
-  launch_shape(c, grid, block);
+  stage_shape(c, grid, block);
   const int track = (mode == 1) ? c->track : 0;
   Phys P = c->phys;
   Planes pl{}, rp{};
