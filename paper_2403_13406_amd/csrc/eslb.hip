@@ -820,10 +820,11 @@ void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   }
 }
 
-// The stage kernel on D2Q4 grids: 64 x 2 blocks (two waves, each one 64-node row
-// segment).  Its waves run for very different times (root searches), and a
-// smaller block frees its CU slots sooner: 1% faster than 64 x 4 on the 4096^2
-// Euler and SW2D passes; D1Q2 keeps 256 threads (smaller blocks measured slower).
+// The stage and adjoint-stage kernels on D2Q4 grids: 64 x 2 blocks (two waves,
+// each one 64-node row segment).  Their waves run for very different times (root
+// searches), and a smaller block frees its CU slots sooner: 1% faster than 64 x 4
+// on the 4096^2 Euler and SW2D passes, 0.7% on the 1024^2 Euler forward + adjoint;
+// D1Q2 keeps 256 threads (smaller blocks measured slower).
 void stage_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   launch_shape(c, grid, block);
   if (c->d == 2 && c->pb.nx >= 64) {
@@ -1003,7 +1004,7 @@ int run_pass(eslb_ctx* c, double* f, int shift, int op) {
 int launch_adjoint_stage(eslb_ctx* c, const double* h, double* gbar, int op, const double* lamr = nullptr) {
   const Grid g = make_grid(c, const_cast<double*>(h));
   dim3 grid, block;
-  launch_shape(c, grid, block);
+  stage_shape(c, grid, block);
   Phys P = c->phys;
   int mode = c->pb.relax;
   if (op == PASS_PROJECT) {
