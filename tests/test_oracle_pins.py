@@ -123,16 +123,17 @@ def test_table6_linear_sixth_order_regime(row):
 
 # ------------------------------------------------------------ linear Fourier symbols
 
-def amplification(a, V, N, m):
-    """Amplification matrix of the oracle's own composed step on the Fourier mode m."""
+def amplification(a, V, N, m, scheme=1, step=None, omega=2.0):
+    """Amplification matrix of the oracle's own step on the Fourier mode m (composed step of the
+    given scheme, or ``step(relaxer, f)``)."""
     x = np.arange(N) / N
     e = np.exp(2j * np.pi * m * x)
-    r = Relaxer(D1, Advection((a,)), V)
+    r = Relaxer(D1, Advection((a,)), V, omega=omega)
     P = np.zeros((2, 2), complex)
     for c in range(2):
         f = np.zeros((2, 1, 1, N), complex)
         f[c, 0, 0] = e
-        g = composed_step(r, f)
+        g = composed_step(r, f, scheme=scheme) if step is None else step(r, f)
         P[:, c] = g[:, 0, 0, 0] / e[0]
     return P
 
@@ -182,6 +183,103 @@ def test_scheme_I_root_expansion():
     # Richardson on the O(xi dt)^2 correction
     assert rel((4 * im5[1] - im5[0]) / 3, c5) < 2e-4
     assert rel((4 * re6[1] - re6[0]) / 3, c6) < 2e-3
+
+
+def _root_coefficients(a, V, scheme, Ns=(192, 384, 768)):
+    """Fifth- and sixth-order coefficients of z1 - exp(-i a xi dt) by Richardson on the (xi dt)^2
+    term (the fifth-order one from the two finer grids, the sixth-order one, whose difference is
+    smaller, from the two coarser ones) and the largest modulus of the other root, from the oracle's
+    amplification matrices."""
+    im5, re6, z2 = [], [], 0.0
+    for N in Ns:
+        xdt = 2 * np.pi / N * 24 / V
+        z = np.linalg.eigvals(amplification(a, V, N, 1, scheme))
+        ref = np.exp(-1j * a * xdt)
+        i1 = int(np.argmin(np.abs(z - ref)))
+        im5.append((z[i1] - ref).imag / xdt ** 5)
+        re6.append((z[i1] - ref).real / xdt ** 6)
+        z2 = max(z2, float(abs(z[1 - i1])))
+    return (4 * im5[2] - im5[1]) / 3, (4 * re6[1] - re6[0]) / 3, z2
+
+
+@pytest.mark.parametrize("a", [0.3, 0.45])
+def test_scheme_II_root_expansion(a):
+    """Sec. 6.2, Scheme II: z2 = 0, z1 has Scheme I's fifth- and sixth-order terms."""
+    g = dict((r[0], r[1]) for r in read_golden("linear_symbols.txt"))
+    V = 1.0
+    poly = 24 * a ** 4 - 25 * a ** 2 * V ** 2 + V ** 4
+    c5, c6, z2 = _root_coefficients(a, V, 2)
+    assert z2 < 1e-14
+    assert rel(c5, a * poly / float(g["root5_denominator"])) < 5e-4
+    assert rel(c6, a ** 2 * poly / float(g["root6_denominator"])) < 5e-4
+
+
+@pytest.mark.parametrize("a", [math.sqrt(6.0) / 12.0, 0.3, 0.45])
+def test_scheme_III_root_expansion(a):
+    """Sec. 6.2, Scheme III: z2 = 0, Scheme I's fifth-order term and the sixth-order term
+    a^2 (63 a^4 - 65 a^2 V^2 + 2 V^4) / 1244160.  At |a| = sqrt(6) V / 12 the fifth-order
+    term vanishes and the sixth-order one is all that is left (the scheme stays fifth order there,
+    Table 6).  Placing the projections between the bricks only moves this coefficient by 1-3 %."""
+    row = [r for r in read_golden("linear_symbols.txt") if r[0] == "scheme3_root6"][0]
+    k4, k2, k0, den = (float(v) for v in row[1:])
+    V = 1.0
+    poly = 24 * a ** 4 - 25 * a ** 2 * V ** 2 + V ** 4
+    want6 = a ** 2 * (k4 * a ** 4 + k2 * a ** 2 * V ** 2 + k0 * V ** 4) / den
+    c5, c6, z2 = _root_coefficients(a, V, 3)
+    assert z2 < 1e-14
+    assert rel(c6, want6) < 5e-4, (c6, want6)
+    if abs(poly) > 1e-12:
+        assert rel(c5, a * poly / 622080.0) < 5e-4
+    else:
+        assert abs(c5) < 1e-3 * abs(want6)
+
+
+def test_scheme_A_symbol_closed_form():
+    """Sec. 6.3, Scheme (A): one step R_omega T(dt), dt = kappa dx / V, on linear D1Q2.
+
+    Hand derivation: T(dt) multiplies the Fourier mode of f_+ by c = exp(-i theta) and that of
+    f_- by conj(c) (pull shift by one cell, theta = xi dx); R_omega = (1 - omega) I + omega E with
+    E = [[w+, w+], [w-, w-]], w+- = (1 +- a/V)/2 (f^eq_+- = w+- u).  So
+        A = [[(1 - omega + omega w+) c, omega w+ conj(c)], [omega w- c, (1 - omega + omega w-) conj(c)]],
+    det A = 1 - omega, tr A = (2 - omega) cos theta - i omega (a/V) sin theta."""
+    from oracle.scheme import scheme_A_step
+    for a, V, omega, N, m in ((0.3, 1.0, 1.93, 40, 3), (-0.7, 1.3, 1.5, 24, 5), (0.9, 1.0, 2.0, 64, 7)):
+        P = amplification(a, V, N, m, step=scheme_A_step, omega=omega)
+        th = 2 * np.pi * m / N
+        c = np.exp(-1j * th)
+        wp, wm = 0.5 * (1 + a / V), 0.5 * (1 - a / V)
+        want = np.array([[(1 - omega + omega * wp) * c, omega * wp * np.conj(c)],
+                         [omega * wm * c, (1 - omega + omega * wm) * np.conj(c)]])
+        assert np.max(np.abs(P - want)) < 1e-14
+        assert abs(np.linalg.det(P) - (1 - omega)) < 1e-14
+        assert abs(np.trace(P) - ((2 - omega) * np.cos(th) - 1j * omega * a / V * np.sin(th))) < 1e-14
+
+
+def test_scheme_B_symbol_closed_form():
+    """Sec. 6.3, Scheme (B): R_1 T(dt/4) R_2 T(dt/2) R_2 T(dt/4), dt = 4 kappa dx / V, linear D1Q2.
+
+    Hand derivation (notation of the Scheme (A) test, sigma_k = c^k w+ + conj(c)^k w- =
+    cos k theta - i (a/V) sin k theta, s = sigma_1): the final projection makes the matrix
+    w r^T with w = (w+, w-) and the row r^T = 1^T T(1) R_2 T(2) R_2 T(1),
+        r = (2 (2 s sigma_2 - sigma_3) c - (2 s - c) c^3,  2 (2 s sigma_2 - sigma_3) conj(c) - (2 s - conj(c)) conj(c)^3),
+    so det = 0 and the non-zero root is tr = 4 s^2 sigma_2 - 4 s sigma_3 + sigma_4 (c^4 at a = V: a
+    translation by four cells).  Projecting first instead (T(1) R_2 T(2) R_2 T(1) R_1) has the same
+    roots but a matrix whose rows are multiples of 1^T: the full matrix tells the two apart."""
+    from oracle.scheme import scheme_B_step
+    for a, V, N, m in ((0.3, 1.0, 40, 3), (-0.7, 1.3, 24, 5), (0.95, 1.0, 64, 7), (1.0, 1.0, 16, 1)):
+        P = amplification(a, V, N, m, step=scheme_B_step)
+        th = 2 * np.pi * m / N
+        c, cb = np.exp(-1j * th), np.exp(1j * th)
+        wp, wm = 0.5 * (1 + a / V), 0.5 * (1 - a / V)
+        sig = lambda k: np.cos(k * th) - 1j * (a / V) * np.sin(k * th)
+        s = sig(1)
+        b = 2 * (2 * s * sig(2) - sig(3))
+        r = np.array([b * c - (2 * s - c) * c ** 3, b * cb - (2 * s - cb) * cb ** 3])
+        want = np.outer([wp, wm], r)
+        assert np.max(np.abs(P - want)) < 1e-14
+        assert abs(np.trace(P) - (4 * s * s * sig(2) - 4 * s * sig(3) + sig(4))) < 1e-14
+        if a == V:
+            assert abs(np.trace(P) - c ** 4) < 1e-14
 
 
 # ------------------------------------------------------------- transport and symmetry
@@ -448,10 +546,19 @@ def test_shallow_water_branch_matches_polynomial_roots():
 
 
 def test_euler_branch_round_trip_and_other_root_inadmissible():
-    """Euler population state: f^eq(U_k) = x and the discarded root violates rho W^2 > gamma p."""
+    """Euler population state: f^eq(U_k) = x, and the discarded root violates rho W^2 > gamma p.
+
+    Both candidates come from the equilibrium's definition, not from the oracle's quadratic:
+    with z the normal velocity, W = 2wV + sigma z, the relations x_1 = rho W / (2V),
+    x_n = z x_1 + sigma p / (2V), x_t = u_t x_1, x_E = (E W + sigma z p) / (2V) give
+    p = 2 sigma V (x_n - z x_1), rho W = 2 V x_1, and the energy relation
+    p W / (gamma - 1) + V x_1 (z^2 + u_t^2) + sigma z p - 2 V x_E = 0, a quadratic in z
+    multiplied out here with numpy's polynomial arithmetic."""
+    from numpy.polynomial import Polynomial as Pn
     rng = np.random.default_rng(9)
     eu = Euler(1.4, 2)
-    V = 3.2
+    gm, V = 1.4, 3.2
+    W0 = 2 * D2.w * V
     for trial in range(20):
         rho, p = rng.uniform(0.9, 1.1, size=2)
         vel = rng.uniform(-0.1, 0.1, size=2)
@@ -465,6 +572,22 @@ def test_euler_branch_round_trip_and_other_root_inadmissible():
             Ek = 0.5 * rp * np.sum(velp ** 2, axis=0) + pp / 0.4
             U = np.concatenate([rp, rp * velp[0], rp * velp[1], Ek])[:, None]
             assert np.max(np.abs(equilibrium(D2, eu, V, U)[k] - x)) < 1e-14
+            n, sg = D2.axis[k], D2.sign[k]
+            x1, xn, xt, xE = x[0, 0], x[1 + n, 0], x[2 - n, 0], x[3, 0]
+            z = Pn([0.0, 1.0])
+            Wz = W0 + sg * z
+            pz = 2 * sg * V * (xn - z * x1)
+            quad = pz * Wz / (gm - 1) + V * x1 * (z * z + (xt / x1) ** 2) + sg * z * pz - 2 * V * xE
+            roots = quad.roots()
+            assert np.all(np.abs(np.imag(roots)) == 0)
+            roots = np.real(roots)
+            i = int(np.argmin(np.abs(roots - velp[n, 0])))
+            assert abs(roots[i] - velp[n, 0]) < 1e-12
+            zo = roots[1 - i]
+            Wo, po = W0 + sg * zo, 2 * sg * V * (xn - zo * x1)
+            rho_o = 2 * V * x1 / Wo
+            admissible = (Wo > 0) and (po > 0) and (rho_o > 0) and (rho_o * Wo ** 2 > gm * po)
+            assert not admissible, (k, zo, Wo, po, rho_o)
 
 
 def test_newton_root_equals_dichotomy():
@@ -520,6 +643,50 @@ def test_fourth_order_convergence_entropic_burgers():
         errs.append(l2_error(fn.sum(0)[0, 0], burgers_exact(u0, x, n * dt), dx))
     slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
     assert -4.4 < slope < -3.6, (errs, slope)
+
+
+def test_fourth_order_self_convergence_entropic_shallow_water():
+    """Err-Estim slope (Sec. 3.2, Table 2's definition: the N run against every other node of the
+    2N run) of the entropic scheme on Table 2's shallow-water setting: g = 1, V = 1.2,
+    h0 = 1/2 + sin(2 pi x)/5, u0 = 0, T = 5/16, error on the velocity u = hu / h."""
+    V, T = 1.2, 5.0 / 16.0
+    sysw = ShallowWater(1.0, 1)
+    vel, dxs = {}, {}
+    for N in (128, 256, 512, 1024):
+        x, dx = grid(N)
+        h = 0.5 + 0.2 * np.sin(2 * np.pi * x)
+        f = equilibrium(D1, sysw, V, np.stack([h, 0.0 * h])[:, None, :])
+        u = run(Relaxer(D1, sysw, V, "entropic"), f, steps_for_time(T, time_step(dx, V))).sum(0)[:, 0]
+        vel[N], dxs[N] = u[1] / u[0], dx
+    Ns = (128, 256, 512)
+    errs = [err_estim(vel[N], vel[2 * N], dxs[N]) for N in Ns]
+    slope = -np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert 3.6 < slope < 4.6, (errs, slope)
+
+
+def test_fourth_order_self_convergence_entropic_euler_d2q4():
+    """Err-Estim slope of the entropic D2Q4^4 Euler scheme (gamma = 1.4, V = 3.2) on smooth periodic
+    data that vary along x only, on a strip three nodes high (every population of the 2D lattice
+    moves and relaxes; refinement along x costs N, not N^2): rho = 1 + sin(2 pi x)/10,
+    u = cos(2 pi x)/10, v = sin(2 pi x + 1)/20, p = 1 + cos(2 pi x)/10, to T = 48 / (32 V)."""
+    V = 3.2
+    eu = Euler(1.4, 2)
+    out, dxs = {}, {}
+    for N in (64, 128, 256, 512):
+        x = np.arange(N) / N
+        rho, uu = 1 + 0.1 * np.sin(2 * np.pi * x), 0.1 * np.cos(2 * np.pi * x)
+        vv, p = 0.05 * np.sin(2 * np.pi * x + 1.0), 1 + 0.1 * np.cos(2 * np.pi * x)
+        U = np.stack([rho, rho * uu, rho * vv, 0.5 * rho * (uu ** 2 + vv ** 2) + p / 0.4])
+        U = np.repeat(U[:, None, :], 3, axis=1)
+        f = equilibrium(D2, eu, V, U)
+        dx = 1.0 / N
+        n = steps_for_time(48.0 / (32 * V), time_step(dx, V))
+        out[N], dxs[N] = run(Relaxer(D2, eu, V, "entropic"), f, n).sum(0)[:, 0, :], dx
+    Ns = (64, 128, 256)
+    for m in range(4):
+        errs = [err_estim(out[N][m], out[2 * N][m], dxs[N]) for N in Ns]
+        slope = -np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+        assert 3.6 < slope < 4.6, (m, errs, slope)
 
 
 # ------------------------------------------------------- projection variants (Sec. 6.1)
