@@ -10,15 +10,12 @@ seeded synthetic smooth fields resident in HBM before timing starts.
 One JSON line:
   value        cells * K / timed seconds / 1e6 (MLUPS, whole job, one GPU)
   roofline     the stage kernel, timed with HIP events on the solver's stream
-               around the timed steps (stage kernels only).  When profiles/ holds a
-               VALU counter record of the same kernel sources, "bound": "alu":
-               FP64 FLOPs per node (ADD + MUL + 2 FMA + TRANS lane instructions)
-               x nodes per launch / average launch time vs 78.6 TFLOP/s; otherwise
-               the HBM figure below.
-  hbm          algorithmic bytes per launch (2 q M 8 B per node) / average launch
-               time vs 8 TB/s; traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per
-               launch (calibrated on a plain copy), from profiles/ when the kernel
-               sources still match
+               around the timed steps (stage kernels only): algorithmic bytes per
+               launch (2 q M 8 B per node) / average launch time vs 8 TB/s;
+               traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated
+               on a plain copy), from profiles/ when the kernel sources still match
+  alu          (when profiles/ holds a VALU counter record of the same sources) the
+               same launches against the FP64 vector peak and the VALU issue peak
   cpu_baseline the CPU oracle, single-threaded, on a bounded sample of the workload
   batch        (default run) a reduced sample of the batched ensemble: one
                batch run (one stage kernel per pass over all instances) vs the plain
@@ -143,24 +140,35 @@ def bench_single(args, torch):
     tag = "%s_%dx%d" % (w.name, w.nx, w.ny)
     traffic = counter_record("traffic", tag)
     valu = counter_record("valu", tag)
-    hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4),
-           "traffic": round(traffic["bytes_per_launch"]) if traffic else None}
+    # the headline roofline: algorithmic bytes (2 q M 8 B per node, read and write of
+    # every population once) over the stage kernel's average launch time, against HBM
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic["bytes_per_launch"]) if traffic else None,
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    if traffic:
+        roofline["traffic_over_algorithmic"] = round(traffic["bytes_per_launch"] / bytes_per_launch, 4)
+    alu = None
     if valu:
-        # the entropic pass is bound by FP64 arithmetic: FLOPs per node from the counters
+        # secondary views of the same launches: the entropic pass is limited by FP64
+        # arithmetic issue, not by its bytes.  FP64 FLOPs per node (ADD + MUL + 2 FMA +
+        # TRANS lane instructions) against the 78.6 TFLOP/s vector peak, and VALU issue
+        # slots (every VALU instruction takes a SIMD's 16 lanes four cycles per wave, an
+        # FP64 transcendental four times that) against the issue peak at 2.4 GHz and at
+        # the clock the counters measured (GRBM_GUI_ACTIVE over the kernel time)
         tflops = valu["fp64_flop_per_node"] * w.cells / avg_launch_s / 1e12
-        roofline = {"bound": "alu", "achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "traffic": hbm["traffic"],
-                    "flop_per_node": valu["fp64_flop_per_node"]}
-        # the same pass against the VALU issue rate: every VALU instruction takes a
-        # SIMD's 16 lanes four cycles per wave, an FP64 transcendental four times that
         li = valu["lane_instructions_per_node"]
         slots = li["SQ_INSTS_VALU"] + 3.0 * li["SQ_INSTS_VALU_TRANS_F64"]
         issue = slots * w.cells / avg_launch_s / 1e12
-        roofline["valu_issue"] = {"achieved": round(issue, 2), "peak": VALU_ISSUE_PEAK, "unit": "T lane-slots/s",
-                                  "frac": round(issue / VALU_ISSUE_PEAK, 4), "slots_per_node": slots}
-    else:
-        roofline = hbm
+        alu = {"fp64": {"achieved": round(tflops, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(tflops / FP64_PEAK_TFLOPS, 4), "flop_per_node": valu["fp64_flop_per_node"]},
+               "valu_issue": {"achieved": round(issue, 2), "peak": VALU_ISSUE_PEAK, "unit": "T lane-slots/s",
+                              "frac": round(issue / VALU_ISSUE_PEAK, 4), "slots_per_node": slots}}
+        clk = valu.get("clock_ghz")
+        if clk:
+            peak_clk = VALU_ISSUE_PEAK * clk / 2.4
+            alu["valu_issue"].update({"clock_ghz_measured": clk, "peak_at_measured_clock": round(peak_clk, 2),
+                                      "frac_at_measured_clock": round(issue / peak_clk, 4)})
     rec = {
         "metric": METRIC,
         "value": round(w.cells * args.steps / (ms / 1e3) / 1e6, 3),
@@ -177,10 +185,11 @@ def bench_single(args, torch):
         "config": {"workload": tag, "lattice": w.lattice, "system": w.system, "nx": w.nx, "ny": w.ny,
                    "V": w.V, "relax": w.relax, "steps_in_workload": w.nsteps, "passes_per_step": passes},
         "roofline": roofline,
-        "hbm": hbm,
         "stage_kernel_avg_us": round(avg_launch_s * 1e6, 2),
         "status": status,
     }
+    if alu:
+        rec["alu"] = alu
     del f
     return rec, w
 

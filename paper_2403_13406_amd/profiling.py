@@ -4,7 +4,7 @@
     python -m paper_2403_13406_amd.profiling traffic --fetch <fetch counter_collection.csv>
         --write <write counter_collection.csv> --kernel k_stage --copy-bytes N --workload TAG --out FILE.json
     python -m paper_2403_13406_amd.profiling valu --csv <counter_collection.csv> --kernel k_stage
-        --nodes N --workload TAG --out FILE.json
+        --nodes N --workload TAG --out FILE.json [--kernel-us T]
 
 HBM traffic of a kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) averaged over
 the kernel's dispatches, each scaled by known-bytes / counter-reading of a plain
@@ -94,16 +94,29 @@ def traffic(fetch_csv, write_csv, kernel, copy_bytes):
     }
 
 
-def valu(valu_csv, kernel, nodes):
-    """FP64 VALU instructions per node of a kernel (SQ_INSTS_VALU_*_F64 count wave instructions)."""
+XCDS = 8  # GRBM_GUI_ACTIVE is summed over the eight accelerator complex dies of an MI355X
+
+
+def valu(valu_csv, kernel, nodes, kernel_us=None):
+    """FP64 VALU instructions per node of a kernel (SQ_INSTS_VALU_*_F64 count wave instructions).
+
+    With GRBM_GUI_ACTIVE in the same pass and the kernel's average duration (from a
+    kernel trace), the clock the chip held: busy cycles per die / duration."""
     c = counters(valu_csv)
     k = _pick(c, kernel)
     mean = lambda v: sum(v) / len(v)
     per = {name: mean(vals) * 64.0 / nodes for name, vals in c[k].items() if name.startswith("SQ_INSTS")}
     flop = (per.get("SQ_INSTS_VALU_ADD_F64", 0.0) + per.get("SQ_INSTS_VALU_MUL_F64", 0.0)
             + 2.0 * per.get("SQ_INSTS_VALU_FMA_F64", 0.0) + per.get("SQ_INSTS_VALU_TRANS_F64", 0.0))
-    return {"kernel": k, "dispatches": len(next(iter(c[k].values()))), "nodes": nodes,
-            "lane_instructions_per_node": per, "fp64_flop_per_node": flop}
+    rec = {"kernel": k, "dispatches": len(next(iter(c[k].values()))), "nodes": nodes,
+           "lane_instructions_per_node": per, "fp64_flop_per_node": flop}
+    if "GRBM_GUI_ACTIVE" in c[k]:
+        cyc = mean(c[k]["GRBM_GUI_ACTIVE"]) / XCDS
+        rec["gui_active_cycles_per_die"] = cyc
+        if kernel_us:
+            rec["kernel_us"] = kernel_us
+            rec["clock_ghz"] = round(cyc / (kernel_us * 1e3), 3)
+    return rec
 
 
 def main(argv=None):
@@ -124,9 +137,11 @@ def main(argv=None):
     v.add_argument("--nodes", type=int, required=True)
     v.add_argument("--workload", required=True)
     v.add_argument("--out", required=True)
+    v.add_argument("--kernel-us", type=float, default=None,
+                   help="average duration of the kernel (trace of the same command), for the clock")
     a = ap.parse_args(argv)
     if a.cmd == "valu":
-        rec = valu(a.csv, a.kernel, a.nodes)
+        rec = valu(a.csv, a.kernel, a.nodes, a.kernel_us)
         rec["workload"] = a.workload
         rec["source_hash"] = source_hash()
         with open(a.out, "w") as fh:
