@@ -181,6 +181,24 @@ int eslb_set_offsets(eslb_ctx* ctx, const int64_t* offsets);
 
 /* Synchronous diagnostics (see eslb_diag).  Returns the sticky status. */
 int eslb_diagnostics(eslb_ctx* ctx, const double* f_dev, eslb_diag* out);
+/* Allocation-free variant of eslb_diagnostics, for callers that cannot allocate
+ * device memory or synchronise: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Enqueues on the context's stream the
+ * same two reduction kernels and writes their sums, in the order
+ * mass[0..M-1], micro entropy, macro entropy (M + 2 doubles, the values
+ * eslb_diagnostics returns in those fields, to the bit), to sums_dev, a
+ * caller-owned device buffer of at least M + 2 doubles.  No allocation, copy,
+ * memset or synchronisation: the per-block partial sums (at most 1024 blocks of
+ * M + 2 values) live in a library-owned static device array of 6144 doubles
+ * (48 KiB per device, held until the process ends).  Every call on a device
+ * shares that device's array: calls that overlap in time on one device race
+ * (order them, e.g. on one stream).  The nodes outside the convexity domain,
+ * inadmissible and non-finite are counted into the context's status block as by
+ * eslb_diagnostics; read them with eslb_diagnostics or the sticky status with
+ * eslb_sync_status.  Returns ESLB_ERR_INVALID_ARG for NULL arguments,
+ * ESLB_ERR_HIP if a launch fails or the array's address cannot be resolved on
+ * the current device. */
+int eslb_diagnostics_noalloc(eslb_ctx* ctx, const double* f_dev, double* sums_dev);
 /* Track omega min/max in every entropic pass (costs a few atomics per block). */
 int eslb_set_stats(eslb_ctx* ctx, int32_t on);
 /* Zero the device counters and the sticky status.  Asynchronous. */

@@ -48,6 +48,7 @@ _SIGNATURES = {
     "eslb_get_offsets": (c_int32, [c_void_p, P(c_int64)]),
     "eslb_set_offsets": (c_int32, [c_void_p, P(c_int64)]),
     "eslb_diagnostics": (c_int32, [c_void_p, c_void_p, P(Diag)]),
+    "eslb_diagnostics_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "eslb_set_stats": (c_int32, [c_void_p, c_int32]),
     "eslb_reset_counters": (c_int32, [c_void_p]),
     "eslb_sync_status": (c_int32, [c_void_p]),

@@ -19,6 +19,7 @@
 #include <cstdint>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -767,6 +768,14 @@ __global__ void k_reset_now(DevStats* st) {
   st->n_nan = 0;
 }
 
+// Block partials of the diagnostics reduction for the allocation-free entry point
+// (eslb_diagnostics_noalloc): at most kDiagMaxBlocks blocks of M + 2 <= 6 values.
+// One copy per device, held until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device.
+constexpr int kDiagMaxBlocks = 1024;
+constexpr int kScratchDoubles = kDiagMaxBlocks * 6;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -784,6 +793,29 @@ static int set_err(eslb_ctx* c, int code, const std::string& msg) {
 static int hip_check(eslb_ctx* c, hipError_t e, const char* what) {
   if (e == hipSuccess) return ESLB_OK;
   return set_err(c, ESLB_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Device address of `scratch` on each device, resolved once per device with that
+// device current (the array's name is not a device address in host code).
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_dev[kMaxDevices] = {};
+
+static hipError_t scratch_address(double** out) {
+  *out = nullptr;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
 }
 
 static long long pmod(long long a, long long n) {
@@ -1438,8 +1470,11 @@ int eslb_create(const eslb_problem* p, void* stream, eslb_ctx** out) {
       c->fused_L_small = kFusedThreads - 2 * H;  // window of one cell per thread
     }
   }
-  c->diag_blocks = 1024;
+  c->diag_blocks = kDiagMaxBlocks;
   const int nv = M + 2;
+  // set-up of the allocation-free diagnostics: the static scratch's address on
+  // the current device (a failure surfaces in that entry point, not here)
+  (void)scratch_address(&c->scratch);
   hipError_t e = hipMalloc(&c->st, sizeof(DevStats));
   if (e == hipSuccess) e = hipMalloc(&c->partials, sizeof(double) * ((size_t)c->diag_blocks * nv + nv));
   if (e != hipSuccess) {
@@ -1675,6 +1710,37 @@ int eslb_diagnostics(eslb_ctx* c, const double* f, eslb_diag* out) {
   return eslb_sync_status(c);
 }
 
+
+int eslb_diagnostics_noalloc(eslb_ctx* c, const double* f, double* sums) {
+  if (!c || !f || !sums) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");
+  if (!c->scratch) {
+    // set-up failed at eslb_create (or a context made on another device): resolve now
+    const int rc = hip_check(c, scratch_address(&c->scratch), "static scratch address");
+    if (rc != ESLB_OK) return rc;
+  }
+  const Grid g = make_grid(c, const_cast<double*>(f));
+  const long long ncell = (long long)c->pb.nx * c->pb.ny;
+  long long nb = (ncell + kDiagThreads - 1) / kDiagThreads;
+  if (nb > c->diag_blocks) nb = c->diag_blocks;
+  const int nblocks = (int)nb;
+  const int nv = c->M + 2;
+  if ((long long)nblocks * nv > kScratchDoubles)
+    return set_err(c, ESLB_ERR_INVALID_ARG, "diagnostics partials exceed the static scratch (" +
+                                                std::to_string(kScratchDoubles) + " doubles)");
+  // every block writes all nv of its partials, so the scratch needs no clearing
+  hipLaunchKernelGGL(k_reset_now, dim3(1), dim3(1), 0, c->stream, c->st);
+  int rc = hip_check(c, hipGetLastError(), "reset kernel launch");
+  if (rc != ESLB_OK) return rc;
+  Phys P = c->phys;
+  double* part = c->scratch;
+#define CALL(S, D) hipLaunchKernelGGL((k_diag<S, D>), dim3(nblocks), dim3(kDiagThreads), 0, c->stream, g, P, part, c->st)
+  ESLB_DISPATCH(c->kind, CALL)
+#undef CALL
+  rc = hip_check(c, hipGetLastError(), "diagnostics kernel launch");
+  if (rc != ESLB_OK) return rc;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kDiagThreads), 0, c->stream, part, nblocks, nv, sums);
+  return hip_check(c, hipGetLastError(), "diagnostics final launch");
+}
 
 int eslb_relax_adjoint(eslb_ctx* c, const double* h, double* gbar) {
   if (!c || !h || !gbar) return set_err(c, ESLB_ERR_INVALID_ARG, "NULL argument");

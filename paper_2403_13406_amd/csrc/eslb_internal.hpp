@@ -75,6 +75,7 @@ struct eslb_ctx {
   eslb::DevStats* st = nullptr;
   double* partials = nullptr;
   int diag_blocks = 0;
+  double* scratch = nullptr;     // device address of the static diagnostics scratch on this context's device
   int track = 0;
   bool small_run = false;  // whole run in one workgroup's LDS (small states)
   int fused_L = 0, fused_H = 0;  // fused D1Q2 step: owned cells per block, halo (0: not available)

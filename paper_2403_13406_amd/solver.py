@@ -202,6 +202,13 @@ class Solver:
                 "n_fallback": d.n_fallback, "n_outside": d.n_outside, "n_inadmissible": d.n_inadmissible,
                 "n_nan": d.n_nan}
 
+    def diagnostics_sums(self, f, out):
+        """eslb_diagnostics_noalloc: mass[M], micro and macro entropy into the float64 CUDA
+        tensor out (M + 2 values), asynchronously, with no allocation in the library."""
+        _check(self.lib, self.ctx, self.lib.eslb_diagnostics_noalloc(self.ctx, self._ptr(f, self.state_shape),
+                                                                     self._ptr(out, (self.M + 2,))))
+        return out
+
     # -- adjoint
     def relax_adjoint(self, h, gbar):
         _check(self.lib, self.ctx, self.lib.eslb_relax_adjoint(self.ctx, self._ptr(h, self.state_shape),
