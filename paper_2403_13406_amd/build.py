@@ -20,6 +20,12 @@ HIPCC_FLAGS = [
     "-shared",
     # packed FP32 instructions stay off in every HIP object of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression: the same node
+    # arithmetic inlined into different kernels (per-pass, fused, whole-run,
+    # batch) then rounds the same way, which the bitwise comparisons between
+    # those paths rely on (with cross-statement fusion the backend's choice
+    # depends on the surrounding control flow of each kernel)
+    "-ffp-contract=on",
     "-I" + os.path.join(ROOT, "include"),
     "-I" + CSRC,
 ]

@@ -101,6 +101,26 @@ __device__ __forceinline__ void record_omega(DevStats* st, bool act, double om) 
   }
 }
 
+// The relaxation of one node in the stage kernel: through this thread's LDS
+// slots for systems with S::kLdsD (the launch gives lds_slots<S>() doubles per
+// thread of dynamic LDS), in registers otherwise.
+template <class S>
+__device__ __forceinline__ double stage_relax(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
+                                              double& lam) {
+  if constexpr (S::kLdsD) {
+    // blocks of kLdsStride threads (stage_shape), each thread its own slots
+    extern __shared__ double stage_lds[];
+    return relax_node_lds<S>(f, mode, P, flags, lam, stage_lds + threadIdx.y * blockDim.x + threadIdx.x);
+  } else {
+    return relax_node<S>(f, mode, P, flags, lam);
+  }
+}
+
+template <class S>
+constexpr size_t stage_lds_bytes() {
+  return S::kLdsD ? (size_t)kLdsStride * lds_slots<S>() * sizeof(double) : 0;
+}
+
 // One relaxation pass (the shift that precedes it is in g.sh).  Off32: planes
 // of at most kPlane32 nodes (32-bit byte offsets); otherwise 64-bit indices.
 // Rec (the adjoint's recomputation): the pass input is also written to the
@@ -138,10 +158,11 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
 #pragma unroll
           for (int m = 0; m < M; ++m) __builtin_nontemporal_store(f[k][m], &plane_at(rec.p[k * M + m], off[k]));
         double lam;
-        om = relax_node<S>(f, mode, P, flags, lam);
+        om = stage_relax<S>(f, mode, P, flags, lam);
         if (mode == 1) __builtin_nontemporal_store(lam, &lamr[(unsigned)y * (unsigned)g.nx + (unsigned)x]);
       } else {
-        om = relax_node<S>(f, mode, P, flags);
+        double lam;
+        om = stage_relax<S>(f, mode, P, flags, lam);
       }
 #pragma unroll
       for (int k = 0; k < Q; ++k)
@@ -164,10 +185,11 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
 #pragma unroll
           for (int m = 0; m < M; ++m) rec.p[k * M + m][id[k]] = f[k][m];
         double lam;
-        om = relax_node<S>(f, mode, P, flags, lam);
+        om = stage_relax<S>(f, mode, P, flags, lam);
         if (mode == 1) lamr[(long long)y * g.nx + x] = lam;
       } else {
-        om = relax_node<S>(f, mode, P, flags);
+        double lam;
+        om = stage_relax<S>(f, mode, P, flags, lam);
       }
 #pragma unroll
       for (int k = 0; k < Q; ++k)
@@ -629,7 +651,7 @@ __global__ __launch_bounds__(kFused2Threads) void k_fused_2d(const double* __res
       for (int k = 0; k < Q; ++k)
 #pragma unroll
         for (int m = 0; m < M; ++m) f[k][m] = lds[(k * M + m) * WW + (j + dy[k]) * W + (i + dx[k])];
-      relax_node<S>(f, 0, Pp, flags);
+      relax_node_fixed<S>(f, Pp);
 #pragma unroll
       for (int k = 0; k < Q; ++k)
 #pragma unroll
@@ -859,9 +881,11 @@ void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
 // D1Q2 keeps 256 threads (smaller blocks measured slower).
 void stage_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   launch_shape(c, grid, block);
-  if (c->d == 2 && c->pb.nx >= 64) {
-    block = dim3(64, 2, 1);
-    grid = dim3(grid.x, (unsigned)(((long long)c->pb.ny + 1) / 2), 1);
+  if (c->d == 2) {
+    // kLdsStride = 128 threads: 64 x 2, or 32 x 4 on grids narrower than 64
+    const int bx = c->pb.nx >= 64 ? 64 : 32, by = kLdsStride / bx;
+    block = dim3(bx, by, 1);
+    grid = dim3((unsigned)(((long long)c->pb.nx + bx - 1) / bx), (unsigned)(((long long)c->pb.ny + by - 1) / by), 1);
   }
 }
 
@@ -881,19 +905,19 @@ int launch_stage(eslb_ctx* c, double* f, int mode, double* rec, double* lamr) {
     for (int i = 0; i < c->q * c->M; ++i) rp.p[i] = rec + (long long)i * g.plane;
   const bool o32 = g.plane <= kPlane32;
   if (o32 && !rec) {
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true, false>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true, false>), grid, block, stage_lds_bytes<S>(), c->stream, g, pl, P, mode, track, c->st, rp, lamr)
     ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
   } else if (!rec) {
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false, false>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false, false>), grid, block, stage_lds_bytes<S>(), c->stream, g, pl, P, mode, track, c->st, rp, lamr)
     ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
   } else if (o32) {
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true, true>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, true, true>), grid, block, stage_lds_bytes<S>(), c->stream, g, pl, P, mode, track, c->st, rp, lamr)
     ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
   } else {
-#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false, true>), grid, block, 0, c->stream, g, pl, P, mode, track, c->st, rp, lamr)
+#define CALL(S, D) hipLaunchKernelGGL((k_stage<S, D, false, true>), grid, block, stage_lds_bytes<S>(), c->stream, g, pl, P, mode, track, c->st, rp, lamr)
     ESLB_DISPATCH(c->kind, CALL)
 #undef CALL
   }

@@ -49,6 +49,13 @@ __device__ __forceinline__ double rcp(double x) {
   return fma(r, fma(e, e, e), r);
 }
 
+// Reciprocal refined by one Newton step (relative error about 2^-48), where that
+// is all the precision the result needs.
+__device__ __forceinline__ double rcp1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // sqrt of a positive normal number: hardware rsq estimate (relative error below
 // 2^-24), one Goldschmidt refinement of (sqrt x, 1/(2 sqrt x)) (error ~2^-48)
 // and a final residual correction s + (x - s^2)/(2 sqrt x) (error ~2^-96).
@@ -63,8 +70,9 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 }
 
 // phi(z) = z - log1p(z) for a pair of arguments.  For |z| < 2^-7 (increments
-// near equilibrium) phi(z) = z^2 g(z) with g(z) = sum_j (-1)^j z^j / (j + 2)
-// replaced by its Chebyshev-economised degree-6 polynomial on [-2^-7, 2^-7]
+// near equilibrium) phi(z) = z^2 g(z) with g(z) = sum_j (-1)^j z^j / (j + 2),
+// its Taylor polynomial to z^4 for |z| <= 2^-10.5, otherwise
+// its Chebyshev-economised degree-6 polynomial on [-2^-7, 2^-7]
 // (relative error below 2^-52 in binary64; no cancellation between z and
 // log1p(z)); otherwise z - log1p(z) with log1p_far for both.
 __device__ __forceinline__ double phi_poly(double z) {
@@ -112,8 +120,23 @@ __device__ inline double log1p_far(double z) {
   return fma(de, 0x1.62e42fee00000p-1, rest);
 }
 
+// phi(z) = z^2 g(z) for |z| <= 2^-10.5 from the Taylor polynomial of g to z^4
+// (truncation below 2 |z|^5 / 7 < 2^-54 relative)
+__device__ __forceinline__ double phi_taylor4(double z) {
+  double g = 1.0 / 6.0;
+  g = fma(g, z, -0.2);
+  g = fma(g, z, 0.25);
+  g = fma(g, z, -1.0 / 3.0);
+  g = fma(g, z, 0.5);
+  return (z * z) * g;
+}
+
 __device__ __forceinline__ void phi_pair(double za, double zb, double& pa, double& pb) {
-  if ((fabs(za) < 0.0078125) & (fabs(zb) < 0.0078125)) {
+  constexpr double kTaylor = 0x1.6a09e667f3bcdp-11;  // 2^-10.5
+  if ((fabs(za) <= kTaylor) & (fabs(zb) <= kTaylor)) {
+    pa = phi_taylor4(za);
+    pb = phi_taylor4(zb);
+  } else if ((fabs(za) < 0.0078125) & (fabs(zb) < 0.0078125)) {
     pa = phi_poly(za);
     pb = phi_poly(zb);
   } else {
@@ -143,6 +166,8 @@ template <> struct Lat<2> {
 // (Example "Linear transport equation", Sec. 1.2.1 and 1.2.2).
 template <int D> struct Advection {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  static constexpr bool kEagerTol = false;  // see stop_tol
+  static constexpr bool kLdsD = false;
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
   using Fast = Advection;  // no deferred branch (see ShallowWater::Fast)
@@ -179,6 +204,8 @@ template <int D> struct Advection {
 // c1 = w + beta u / (2V); B = dU^2 (w/2 + beta (3u + 2 dU) / (12V)).
 template <int D> struct Burgers {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  static constexpr bool kEagerTol = false;  // see stop_tol
+  static constexpr bool kLdsD = false;
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
   using Fast = Burgers;  // no deferred branch (see ShallowWater::Fast)
@@ -307,6 +334,8 @@ template <int D> struct ShallowWaterFast;
 
 template <int D> struct ShallowWater {
   static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  static constexpr bool kEagerTol = false;  // see stop_tol
+  static constexpr bool kLdsD = false;
   static constexpr int M = D + 1, Q = Lat<D>::Q;
   // rule: set by the Fast variant's evaluations where Newton alone did not give
   // the branch root (the node is then relaxed again with the branch rule)
@@ -493,8 +522,13 @@ template <int D> struct ShallowWaterFast : ShallowWater<D> {
 
 struct Euler2 {
   static constexpr int D = 2, M = 4, Q = 4;
-  static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
-  struct Node { double rho, vel[2], p, E, irho, ip; };
+  // resident 256-thread blocks per CU asked of the stage kernel: three waves per
+  // SIMD (168 VGPRs), which the LDS-held d makes room for
+  static constexpr int kStageBlocks = 3;
+  static constexpr bool kEagerTol = true;  // see stop_tol
+  static constexpr bool kLdsD = true;      // stage kernel keeps d in LDS (relax_node_lds)
+  // cell state: density, velocity, pressure, energy, 1/p and c^2 = gamma p / rho
+  struct Node { double rho, vel[2], p, E, ip, cs2; };
   using Fast = Euler2;  // no deferred branch (see ShallowWater::Fast)
   __device__ static bool pending(const Node&) { return false; }
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
@@ -515,14 +549,14 @@ struct Euler2 {
     c.vel[1] = u[2] * ir;
     c.E = u[3];
     c.p = (P.p0 - 1.0) * (u[3] - 0.5 * u[0] * (c.vel[0] * c.vel[0] + c.vel[1] * c.vel[1]));
-    c.irho = ir;
     c.ip = rcp(c.p);
+    c.cs2 = P.p0 * c.p * ir;
     return (c.rho > 0.0) && (c.p > 0.0);
   }
   // limit of the skip measure: 2^-8 m^2, m = 1 - c^2/W_min^2 (negative: never skip)
   __device__ static double skip_limit(const Node& c, const Phys& P) {
     const double Wmin = P.W0 - fmax(fabs(c.vel[0]), fabs(c.vel[1]));
-    const double m = 1.0 - P.p0 * c.p * c.irho * rcp(Wmin * Wmin);
+    const double m = 1.0 - c.cs2 * rcp(Wmin * Wmin);
     return (Wmin > 0.0 && m > 0.0) ? kSkipZ * m * m : -1.0;
   }
   __device__ static bool subchar(const Node& c, const Phys& P) {
@@ -552,77 +586,145 @@ struct Euler2 {
     out[2] = vj * z[2] - gm1 * vy * A + (j == 1 ? z[0] + zv + z[3] * H : 0.0);
     out[3] = gm1 * z[1 + j] + P.p0 * vj * z[3];
   }
-  // With e = t d, the increment quadratic simplifies (the 2V x_1 u_n terms cancel):
+
+  // Population state of x = f^eq_k + t d_k, in increments from the cell state.
+  // With e = t d the increment quadratic of the normal velocity dn simplifies
+  // (the 2V x_1 u_n terms cancel):
   //   qa = -V x_1 (gamma+1)/(gamma-1),
   //   qb = sigma (gamma (t P0c + p) - 2V x_1 W)/(gamma-1),
   //   qc = t (qc1 + V dtn (2 u_t + du_t)),  du_t = t dtn / x_1,
   // with per-velocity constants gnd = d_n - u_n d_1, dtn = d_t - u_t d_1,
   // P0c = 2 sigma V gnd, qc1 = -2V d_E + V d_1 |u|^2 + P0c (W/(gamma-1) + sigma u_n).
   // Multiplied through by x_1 (qa/x_1 = q0 is a constant, qcx = x_1 qc has no
-  // division), the quadratic needs one reciprocal, 1/(x_1 den), for both dn and
-  // du_t.
+  // division), the quadratic needs one reciprocal, 1/(x_1 den), which also gives
+  // 1/x_1.  The population state's density and pressure then follow without
+  // division: x_1 = rho' W'/(2V) and f_1 = rho W/(2V) give
+  //   zb = rho/rho' - 1 = (sigma rho dn/(2V) - e_1)/x_1,   al = p'/p - 1 = dp/p,
+  //   za = (p'/p)(rho/rho') - 1 = al + zb + al zb.
+  // The thermal part of B is x_1 [phi(za)/(gamma-1) + phi(zb)], phi(z) = z - log1p(z),
+  // and ds = log1p(za) + (gamma-1) log1p(zb).  The entropy variables need
+  // beta' = rho'/p' = beta/(1 + za): the one further reciprocal, only for F'.
+  struct VelC { double W, dtn, P0c, qc1, qb0, qb1, cW, Vdtn; };
+  template <int k>
+  __device__ static VelC vel_consts(const Node& c, double un, double ut, double d0, double dn_, double dt_, double d3,
+                                    const Phys& P) {
+    constexpr double s = Lat<2>::sign(k);
+    const double igm1 = P.p2, V = P.V, V2 = P.V2;
+    VelC K;
+    K.W = P.W0 + s * un;
+    const double gnd = dn_ - un * d0;
+    K.dtn = dt_ - ut * d0;
+    K.P0c = s * V2 * gnd;
+    K.qc1 = -V2 * d3 + V * d0 * (un * un + ut * ut) + K.P0c * (K.W * igm1 + s * un);
+    const double sg = s * igm1 * P.p0;
+    K.qb0 = sg * c.p;          // qb = qb0 + t qb1 - cW x_1
+    K.qb1 = sg * K.P0c;
+    K.cW = s * igm1 * V2 * K.W;
+    K.Vdtn = V * K.dtn;
+    return K;
+  }
+  // B_k(t) and (DV) F'-term (v(U_k) - v(u)) . d_k; false outside the convexity domain
+  template <int k, bool DV>
+  __device__ static bool eval(const Node& c, double un, double ut, double f1, double d0, double dn_, double dt_,
+                              double d3, const VelC& K, double t, double& B, double& dvd, double* dv, const Phys& P,
+                              double zlim, bool& small) {
+    constexpr int n = Lat<2>::axis(k), tt = 1 - n;
+    constexpr double s = Lat<2>::sign(k);
+    const double igm1 = P.p2, V2 = P.V2;
+    const double rho = c.rho;
+    const double e1 = t * d0;
+    const double x1 = f1 + e1;
+    const double tdtn = t * K.dtn;
+    const double qb = fma(-K.cW, x1, fma(t, K.qb1, K.qb0));
+    const double qcx = t * fma(K.Vdtn, fma(2.0 * ut, x1, tdtn), K.qc1 * x1);
+    const double disc = fma(qb, qb, -4.0 * P.q0 * qcx);
+    const bool okd = disc > 0.0;
+    const double den = qb + copysign(okd ? sqrt_pos(disc) : 0.0, qb);
+    const double r1 = rcp(x1 * den);
+    const double ix1 = den * r1;  // 1 / x_1
+    const double dn = -2.0 * qcx * r1;
+    const double dt = tdtn * ix1;
+    const double dp = fma(-s * V2 * x1, dn, t * K.P0c);
+    const double Wp = K.W + s * dn;
+    const double al = dp * c.ip;
+    const double zb = fma(s * rho * P.inv2V, dn, -e1) * ix1;
+    const double za = fma(al, zb, al + zb);
+    small = (fabs(za) <= zlim) & (fabs(zb) <= zlim) & (fabs(e1) <= zlim * f1);
+    double pa, pb;
+    phi_pair(za, zb, pa, pb);
+    const double bet = rho * c.ip;
+    const double du2 = fma(dn, dn, dt * dt);
+    B = fma(x1, fma(du2, 0.5 * bet, fma(pa, igm1, pb)), (s * P.inv2V) * bet * dp * dn);
+    if (DV) {
+      // entropy-variable difference v(U_k) - v(u)
+      const double ds = (za - pa) + (P.p0 - 1.0) * (zb - pb);
+      // F' needs far less than full precision (its errors enter the predicted
+      // lambda multiplied by lambda - 1): a once-refined reciprocal
+      const double dbet = -bet * za * rcp1(1.0 + za);
+      const double unp = un + dn, utp = ut + dt;
+      const double up2 = fma(unp, unp, utp * utp);
+      const double dkin = fma(dbet, up2, bet * fma(dn, 2.0 * un + dn, dt * (2.0 * ut + dt)));
+      dv[0] = fma(-ds, igm1, -0.5 * dkin);
+      dv[1 + n] = fma(dbet, unp, bet * dn);
+      dv[1 + tt] = fma(dbet, utp, bet * dt);
+      dv[3] = -dbet;
+      dvd = fma(dv[0], d0, fma(dv[1 + n], dn_, fma(dv[1 + tt], dt_, dv[3] * d3)));
+    }
+    // rho' > 0, p' > 0 and the sub-characteristic condition rho' W'^2 > gamma p',
+    // i.e. W'^2 > c^2 (1 + za); all conditions evaluated (no short-circuit branches)
+    return okd & (x1 > 0.0) & (Wp > 0.0) & (zb > -1.0) & (al > -1.0) & (Wp * Wp > c.cs2 * (1.0 + za)) & isfinite(B);
+  }
   template <int k, bool DV>
   __device__ static bool bregman(const Node& c, const double* feq, const double* d, double t, double& B, double* dv,
                                  const Phys& P, double zlim, bool& small) {
     constexpr int n = Lat<2>::axis(k), tt = 1 - n;
-    constexpr double s = Lat<2>::sign(k);
-    const double gm = P.p0, igm1 = P.p2, V = P.V, V2 = P.V2;
-    const double rho = c.rho, p = c.p, un = c.vel[n], ut = c.vel[tt];
-    const double W = P.W0 + s * un;
-    const double f1 = feq[0];
     // t-independent per-velocity constants; recomputed at every evaluation (the
     // opaque copy keeps the compiler from hoisting them: keeping them live for
     // all four velocities costs more registers than recomputing them)
     double d0 = d[0], dn_ = d[1 + n], dt_ = d[1 + tt], d3 = d[3];
     asm volatile("" : "+v"(d0), "+v"(dn_), "+v"(dt_), "+v"(d3));
-    const double gnd = dn_ - un * d0;
-    const double dtn = dt_ - ut * d0;
-    const double P0c = s * V2 * gnd;
-    const double qc1 = -V2 * d3 + V * d0 * (un * un + ut * ut) + P0c * (W * igm1 + s * un);
-    // t-dependent part
-    const double e1 = t * d0;
-    const double x1 = f1 + e1;
-    const double tdtn = t * dtn;
-    const double qb = s * igm1 * (gm * (t * P0c + p) - V2 * x1 * W);
-    const double qcx = t * (qc1 * x1 + V * dtn * (2.0 * ut * x1 + tdtn));
-    const double disc = qb * qb - 4.0 * P.q0 * qcx;
-    const bool okd = disc > 0.0;
-    const double den = qb + copysign(okd ? sqrt_pos(disc) : 0.0, qb);
-    const double r1 = rcp(x1 * den);
-    const double dn = -2.0 * qcx * r1;
-    const double dt = tdtn * den * r1;
-    const double dp = t * P0c - s * V2 * x1 * dn;
-    const double Wp = W + s * dn;
-    const double drho = V2 * (e1 * W - s * f1 * dn) * rcp(W * Wp);
-    const double rhop = rho + drho, pp = p + dp;
-    const double al = dp * c.ip, be = drho * c.irho;
-    const double opa = 1.0 + al, opb = 1.0 + be;
-    const double rab = rcp(opa * opb);
-    const double ibb = opa * rab;  // 1/(1+be)
-    // za = (1+al)/(1+be) - 1, zb = 1/(1+be) - 1: the thermal part of B is
-    // x_1 [phi(za)/(gamma-1) + phi(zb)], and ds = log1p(al) - gamma log1p(be)
-    // = log1p(za) + (gamma-1) log1p(zb)
-    const double za = (al - be) * ibb, zb = -be * ibb;
-    small = (fabs(za) <= zlim) & (fabs(zb) <= zlim) & (fabs(e1) <= zlim * f1);
-    double pa, pb;
-    phi_pair(za, zb, pa, pb);
-    const double du2 = dn * dn + dt * dt;
-    B = x1 * fma(pa, igm1, pb) + 0.5 * rho * x1 * du2 * c.ip + s * rho * dp * dn * c.ip * P.inv2V;
-    if (DV) {
-      // entropy-variable difference v(U_k) - v(u)
-      const double ds = (za - pa) + (gm - 1.0) * (zb - pb);
-      const double bet = rho * c.ip;
-      const double dbet = bet * (be - al) * (opb * rab);
-      const double unp = un + dn, utp = ut + dt;
-      const double up2 = unp * unp + utp * utp;
-      const double dkin = dbet * up2 + bet * (dn * (2.0 * un + dn) + dt * (2.0 * ut + dt));
-      dv[0] = -ds * igm1 - 0.5 * dkin;
-      dv[1 + n] = dbet * unp + bet * dn;
-      dv[1 + tt] = dbet * utp + bet * dt;
-      dv[3] = -dbet;
-    }
-    // all conditions evaluated (no short-circuit branches)
-    return okd & (x1 > 0.0) & (Wp > 0.0) & (rhop > 0.0) & (pp > 0.0) & (rhop * Wp * Wp > gm * pp) & isfinite(B);
+    const double un = c.vel[n], ut = c.vel[tt];
+    const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
+    double dvd;
+    return eval<k, DV>(c, un, ut, feq[0], d0, dn_, dt_, d3, K, t, B, dvd, dv, P, zlim, small);
+  }
+  // bregman for values just read from thread-private LDS slots (LdsSrc), the cell
+  // velocity (vel) included: no copies, and nothing derived from them is kept
+  // from one evaluation to the next
+  template <int k, bool DV>
+  __device__ static bool bregman_fresh(const Node& c, const double* vel, const double* feq, const double* d, double t,
+                                       double& B, double* dv, const Phys& P, double zlim, bool& small) {
+    constexpr int n = Lat<2>::axis(k), tt = 1 - n;
+    const VelC K = vel_consts<k>(c, vel[n], vel[tt], d[0], d[1 + n], d[1 + tt], d[3], P);
+    double dvd;
+    return eval<k, DV>(c, vel[n], vel[tt], feq[0], d[0], d[1 + n], d[1 + tt], d[3], K, t, B, dvd, dv, P, zlim, small);
+  }
+  // The predictor's two samples for velocity k, t = +1 and t = -1 (the skip
+  // measure at t = -1 only), from one read of its LDS slots: the per-velocity
+  // constants are formed once and t is a constant in each evaluation.  The second
+  // evaluation starts once the first is summed (interleaved, they need more
+  // registers than three waves per SIMD allow).
+  template <int k>
+  __device__ static void pair_fresh(const Node& c, const double* vel, double f1, const double* d, const Phys& P,
+                                    double zlim, double& F1, double& dF1, bool& ok1, double& Fm, double& dFm,
+                                    bool& okm, bool& small) {
+    constexpr int n = Lat<2>::axis(k), tt = 1 - n;
+    double un = vel[n], ut = vel[tt], d0 = d[0], dn_ = d[1 + n], dt_ = d[1 + tt], d3 = d[3];
+    const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
+    double B, dvd, dv[4];
+    bool sk;
+    // sums in the order of fsum (component by component), so that the register
+    // path (relax_node) gives the same bits
+    ok1 &= eval<k, true>(c, un, ut, f1, d0, dn_, dt_, d3, K, 1.0, B, dvd, dv, P, -1.0, sk);
+    F1 += B;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dF1 += dv[m] * d[m];
+    asm volatile("" : "+v"(f1), "+v"(d0) : "v"(F1), "v"(dF1));
+    okm &= eval<k, true>(c, un, ut, f1, d0, dn_, dt_, d3, K, -1.0, B, dvd, dv, P, zlim, sk);
+    small &= sk;
+    Fm += B;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dFm += dv[m] * d[m];
   }
 };
 
@@ -645,35 +747,127 @@ template <class S> struct Eq {
   }
 };
 
+// Where the root search reads d_k and the mass component of f^eq_k (the only
+// component of f^eq the Bregman terms use): the arrays of node_split (RegSrc),
+// or thread-private LDS slots (LdsSrc), so that only the velocity being
+// evaluated holds them in registers.  get<k>(fence, ...) reads velocity k; for
+// LDS the read address depends on `fence`, so the read cannot be moved ahead of
+// whatever produced that value.
+template <class S> struct RegSrc {
+  static constexpr bool kFresh = false;  // values live in registers: S::bregman makes opaque copies
+  const double (&feq)[S::Q][S::M];
+  const double (&d)[S::Q][S::M];
+  template <int k>
+  __device__ __forceinline__ void get(double, double& f1, double (&dk)[S::M]) const {
+    f1 = feq[k][0];
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) dk[m] = d[k][m];
+  }
+  __device__ __forceinline__ double max_abs_feq() const {
+    double femax = 0.0;
+#pragma unroll
+    for (int k = 0; k < S::Q; ++k)
+#pragma unroll
+      for (int m = 0; m < S::M; ++m) femax = fmax(femax, fabs(feq[k][m]));
+    return femax;
+  }
+};
+
+// LDS slots of one thread: slot j at p[j * kLdsStride] (blocks of kLdsStride
+// threads, one slot of each thread side by side: conflict-free, and every slot
+// an immediate offset from one address).  d_{k,m} at j = k M + m, the mass of
+// f^eq_k at j = Q M + k, the cell velocity at j = Q M + Q + i (i < Q/2, the dimension).
+constexpr int kLdsStride = 128;
+template <class S>
+__host__ __device__ constexpr int lds_slots() { return S::Q * S::M + S::Q + S::Q / 2; }
+
+template <class S> struct LdsSrc {
+  static constexpr bool kFresh = true;  // every get is a fresh read: S::bregman_fresh, no copies
+  double* p;
+  template <int k>
+  __device__ __forceinline__ void get(double fence, double& f1, double (&dk)[S::M], double (&vel)[S::Q / 2]) const {
+    unsigned off = 0;
+    asm volatile("" : "+v"(off) : "v"(fence));
+    const double* q = p + off;
+    f1 = q[(S::Q * S::M + k) * kLdsStride];
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) dk[m] = q[(k * S::M + m) * kLdsStride];
+#pragma unroll
+    for (int i = 0; i < S::Q / 2; ++i) vel[i] = q[(S::Q * S::M + S::Q + i) * kLdsStride];
+  }
+  __device__ __forceinline__ double max_abs_feq() const { return 0.0; }  // eager-tolerance systems only
+};
+
 // F(t) = sum_k B_k and (DV) F'(t) = sum_k (v(U_k) - v(u)) . d_k, velocities k..Q-1.
 // small: AND over the velocities of each system's "population state within
 // zlim of the cell state" test (always false for systems without a skip measure
 // and for zlim < 0).
-template <class S, bool DV = true, int k = 0>
-__device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&feq)[S::Q][S::M],
-                                     const double (&d)[S::Q][S::M], double t, double& F, double& dF, const Phys& P,
-                                     double zlim, bool& small) {
+template <class S, bool DV = true, int k = 0, class Src>
+__device__ __forceinline__ bool fsum(const typename S::Node& c, const Src& src, double t, double& F, double& dF,
+                                     const Phys& P, double zlim, bool& small, bool okacc = true) {
   if constexpr (k == S::Q) {
-    return true;
+    return okacc;
   } else {
-    double dv[S::M], B;
+    double dv[S::M], B, f1, dk[S::M];
     bool sk;
-    const bool ok = S::template bregman<k, DV>(c, feq[k], d[k], t, B, dv, P, zlim, sk);
+    bool ok;
+    if constexpr (Src::kFresh) {
+      double vel[S::Q / 2];
+      src.template get<k>(t, f1, dk, vel);
+      ok = S::template bregman_fresh<k, DV>(c, vel, &f1, dk, t, B, dv, P, zlim, sk);
+    } else {
+      src.template get<k>(t, f1, dk);
+      ok = S::template bregman<k, DV>(c, &f1, dk, t, B, dv, P, zlim, sk);
+    }
     small &= sk;
+    okacc &= ok;
     F += B;
     if (DV) {
 #pragma unroll
-      for (int m = 0; m < S::M; ++m) dF += dv[m] * d[k][m];
+      for (int m = 0; m < S::M; ++m) dF += dv[m] * dk[m];
     }
-    // Serialise the velocities: the next evaluation waits for this one's sum.
-    // Left free, the scheduler interleaves all q inversions for ILP and needs
-    // more registers than two waves per SIMD allow (spills); in sequence they
-    // fit without spilling (measured 1.20x faster on the Euler pass).
+    // Serialise the velocities: the next evaluation waits for this one's sums
+    // and for its validity and skip tests, materialised here (left as booleans
+    // combined at the end, their comparisons sink there and keep the operands of
+    // every velocity live through the sweep).  Left free, the scheduler also
+    // interleaves all q inversions for ILP and needs more registers than the
+    // waves per SIMD allow (spills); in sequence they fit without spilling.
     double ts = t;
-    asm volatile("" : "+v"(ts) : "v"(F), "v"(dF));
-    const bool rest = fsum<S, DV, k + 1>(c, feq, d, ts, F, dF, P, zlim, small);
-    return ok && rest;
+    int okv = okacc, smv = small;
+    asm volatile("" : "+v"(ts), "+v"(okv), "+v"(smv) : "v"(F), "v"(dF));
+    small = smv != 0;
+    return fsum<S, DV, k + 1>(c, src, ts, F, dF, P, zlim, small, okv != 0);
   }
+}
+
+// Both predictor samples, velocity by velocity, for systems with S::pair_fresh
+// reading an LdsSrc: F, F' at t = +1 (F1, dF1, ok1) and t = -1 (Fm, dFm, okm,
+// small), each velocity's reads and evaluations after the previous one's sums
+// and tests (materialised, as in fsum).
+template <class S, int k = 0>
+__device__ __forceinline__ void fsum_pm(const typename S::Node& c, const LdsSrc<S>& src, const Phys& P, double zlim,
+                                        double& F1, double& dF1, bool& ok1, double& Fm, double& dFm, bool& okm,
+                                        bool& small, double fence = 0.0) {
+  if constexpr (k < S::Q) {
+    double f1, dk[S::M], vel[S::Q / 2];
+    src.template get<k>(fence, f1, dk, vel);
+    S::template pair_fresh<k>(c, vel, f1, dk, P, zlim, F1, dF1, ok1, Fm, dFm, okm, small);
+    double fn = 0.0;
+    int o1 = ok1, om = okm, sm = small;
+    asm volatile("" : "+v"(fn), "+v"(o1), "+v"(om), "+v"(sm) : "v"(F1), "v"(dF1), "v"(Fm), "v"(dFm));
+    ok1 = o1 != 0;
+    okm = om != 0;
+    small = sm != 0;
+    fsum_pm<S, k + 1>(c, src, P, zlim, F1, dF1, ok1, Fm, dFm, okm, small, fn);
+  }
+}
+
+// Register-array form (the diagnostics and the adjoint's evaluations).
+template <class S, bool DV = true>
+__device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&feq)[S::Q][S::M],
+                                     const double (&d)[S::Q][S::M], double t, double& F, double& dF, const Phys& P,
+                                     double zlim, bool& small) {
+  return fsum<S, DV, 0>(c, RegSrc<S>{feq, d}, t, F, dF, P, zlim, small);
 }
 
 // u = sum_k f_k, f^eq(u), d = f - f^eq and dmax = max |d| (a maximum of
@@ -703,14 +897,16 @@ __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double
 
 // Tolerance of the stop rule: 2 eps (max |f^eq| + dmax), max |f^eq| + dmax being an
 // upper bound of max(|f^eq|, |f|) within a factor 2.  Only the paths past the
-// predictor shortcut need it, so it is formed there.
+// predictor shortcut need it, so by default it is formed there from the f^eq of
+// node_split (S::kEagerTol: formed at once instead, so that only the mass
+// components of f^eq stay live through the root search).
 template <class S>
-__device__ __forceinline__ double stop_tol(const double (&feq)[S::Q][S::M], double dmax) {
-  double femax = 0.0;
-#pragma unroll
-  for (int k = 0; k < S::Q; ++k)
-#pragma unroll
-    for (int m = 0; m < S::M; ++m) femax = fmax(femax, fabs(feq[k][m]));
+__device__ __forceinline__ double max_abs_feq(const double (&feq)[S::Q][S::M]) {
+  return RegSrc<S>{feq, feq}.max_abs_feq();
+}
+template <class S, class Src>
+__device__ __forceinline__ double stop_tol(const Src& src, double dmax, double femax) {
+  if constexpr (!S::kEagerTol) femax = src.max_abs_feq();
   return 2.0 * 2.220446049250313e-16 * (femax + dmax);
 }
 
@@ -724,26 +920,37 @@ __device__ __forceinline__ double stop_tol(const double (&feq)[S::Q][S::M], doub
 // (far from equilibrium, domain edges) a safeguarded Newton iteration with a
 // bisection bracket takes over.  fallback = true when no root lies inside the
 // convexity domain (omega = 1 then).
-template <class S>
-__device__ inline double entropic_lambda(const typename S::Node& c, const double (&feq)[S::Q][S::M],
-                                         const double (&d)[S::Q][S::M], double dmax, const Phys& P,
-                                         bool& fallback) {
+template <class S, class Src>
+__device__ inline double entropic_lambda(const typename S::Node& c, const Src& src, double dmax, double femax,
+                                         const Phys& P, bool& fallback) {
   fallback = false;
   double F1 = 0.0, dF1 = 0.0;
   bool small = true;  // all population states at t = -1 within the skip measure
   bool unused = true;
-  // S::pending: an evaluation needs the branch rule this variant leaves out
-  // (the caller relaxes the node again with it)
-  if (!fsum<S>(c, feq, d, 1.0, F1, dF1, P, -1.0, unused)) {
-    fallback = !S::pending(c);
-    return 0.0;
+  double Fm = 0.0, dFm = 0.0;
+  bool okm = true;
+  if constexpr (Src::kFresh) {
+    // both samples in one sweep; the t = -1 one is discarded where t = +1 is outside the domain
+    bool ok1 = true;
+    fsum_pm<S>(c, src, P, S::skip_limit(c, P), F1, dF1, ok1, Fm, dFm, okm, small);
+    if (!ok1) {
+      fallback = !S::pending(c);
+      return 0.0;
+    }
+    if (!(F1 > 0.0)) return 1.0;
+  } else {
+    // S::pending: an evaluation needs the branch rule this variant leaves out
+    // (the caller relaxes the node again with it)
+    if (!fsum<S>(c, src, 1.0, F1, dF1, P, -1.0, unused)) {
+      fallback = !S::pending(c);
+      return 0.0;
+    }
+    if (!(F1 > 0.0)) return 1.0;
+    okm = fsum<S>(c, src, -1.0, Fm, dFm, P, S::skip_limit(c, P), small);
   }
-  if (!(F1 > 0.0)) return 1.0;
   double lo = 0.0, hi = INFINITY, x = 1.0;
   bool hi_bad = false;
   {
-    double Fm = 0.0, dFm = 0.0;
-    const bool okm = fsum<S>(c, feq, d, -1.0, Fm, dFm, P, S::skip_limit(c, P), small);
     if (S::pending(c)) return 0.0;
     const double H = Fm - F1;
     if (okm && H == 0.0) return 1.0;
@@ -760,22 +967,37 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
       const double dd = 0.25 * ((G1p + Gmp) - (G1 - Gm));
       const double bb = 0.5 * (G1 - Gm) - dd;
       const double aa = 0.5 * (G1 + Gm) - cc;
-      double lp = 1.0, pd = 1.0, rpd = 1.0;
+      // Newton on lambda^2 g(lambda) = G1 from lambda = 1.  The model's root is
+      // within |lambda - 1| of 1, and its second derivative over twice its first is
+      // about 1/2, so the error after j steps is about 2 (|lambda - 1| / 2)^(2^j):
+      // three steps leave it below 2^-55 wherever |lambda - 1| < 2^-6 (the
+      // predictor's skip region and far beyond); a fourth is taken where the third
+      // step was not already below 2^-26.  The reciprocals need no more than 2^-48.
+      double lp = 1.0, pd = 1.0, rpd = 1.0, st = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < 3; ++j) {
         const double g = aa + lp * (-bb + lp * (cc - dd * lp));
         const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
         const double pv = lp * lp * g - G1;
         pd = 2.0 * lp * g + lp * lp * gp;
-        rpd = rcp(pd);
+        rpd = rcp1(pd);
+        st = pv * rpd;
+        lp -= st;
+      }
+      if (!(fabs(st) <= 0x1p-26)) {
+        const double g = aa + lp * (-bb + lp * (cc - dd * lp));
+        const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
+        const double pv = lp * lp * g - G1;
+        pd = 2.0 * lp * g + lp * lp * gp;
+        rpd = rcp1(pd);
         lp -= pv * rpd;
       }
       if (isfinite(lp) && lp > lo && lp < hi && pd > 0.0) {
         // close to equilibrium the prediction is within the stopping tolerance
         if (small) return lp;
         double F3 = 0.0, dF3 = 0.0;
-        const double tol = stop_tol<S>(feq, dmax);
-        const bool ok3 = fsum<S, false>(c, feq, d, -lp, F3, dF3, P, -1.0, unused);
+        const double tol = stop_tol<S>(src, dmax, femax);
+        const bool ok3 = fsum<S, false>(c, src, -lp, F3, dF3, P, -1.0, unused);
         if (S::pending(c)) return 0.0;
         const double H3 = F3 - F1;
         const double xc = lp - H3 * rpd;
@@ -790,12 +1012,12 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const double
     }
     x = (isfinite(xn) && xn > lo && xn < hi) ? xn : (isinf(hi) ? 2.0 : 0.5 * (lo + hi));
   }
-  const double tol = stop_tol<S>(feq, dmax);
+  const double tol = stop_tol<S>(src, dmax, femax);
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double F = 0.0, dF = 0.0;
     bool unused = false;
-    const bool ok = fsum<S>(c, feq, d, -x, F, dF, P, -1.0, unused);
+    const bool ok = fsum<S>(c, src, -x, F, dF, P, -1.0, unused);
     if (S::pending(c)) return 0.0;
     const double H = F - F1, dH = -dF;
     if (ok && H == 0.0) return x;
@@ -837,37 +1059,36 @@ __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, 
   constexpr int Q = S::Q, M = S::M;
   double u[M], feq[Q][M], d[Q][M], dmax;
   node_split<S>(f, u, feq, d, dmax, P);
-  if (mode == 0) {
-    const double om = P.omega, om1 = 1.0 - P.omega;
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-#pragma unroll
-      for (int m = 0; m < M; ++m) f[k][m] = om1 * f[k][m] + om * feq[k][m];
-    lam_out = om - 1.0;
-    return om;
-  }
-  typename S::Node c;
-  const bool adm = S::prepare(u, c, P);
-  if (!adm) flags |= FLAG_INADMISSIBLE;
-  // At equilibrium (d = 0, so f = f^eq exactly) omega = 2, the limit of the
-  // root; the common update below then returns f^eq = f, so f itself need not
-  // stay live through the root iteration.
+  // Both modes end with the same update f' = f^eq - lambda d, lambda = omega - 1
+  // (for fixed omega, (1 - omega) f + omega f^eq written in d = f - f^eq): no
+  // branch of the fixed mode keeps f or f^eq live through the entropic root search.
   bool fallback = false;
-  double lam = 1.0;
-  if (dmax != 0.0) {
-    fallback = !adm;
-    lam = 0.0;
-    if (adm) lam = entropic_lambda<typename S::Fast>(c, feq, d, dmax, P, fallback);
-    if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, feq, d, dmax, P, fallback);
-    if (fallback) {
+  double lam = P.omega - 1.0;
+  if (mode != 0) {
+    typename S::Node c;
+    const bool adm = S::prepare(u, c, P);
+    if (!adm) flags |= FLAG_INADMISSIBLE;
+    // At equilibrium (d = 0, so f = f^eq exactly) omega = 2, the limit of the
+    // root; the common update below then returns f^eq = f.
+    lam = 1.0;
+    if (dmax != 0.0) {
+      fallback = !adm;
       lam = 0.0;
-      flags |= FLAG_FALLBACK;
+      const double femax = S::kEagerTol ? max_abs_feq<S>(feq) : 0.0;
+      const RegSrc<S> src{feq, d};
+      if (adm) lam = entropic_lambda<typename S::Fast>(c, RegSrc<typename S::Fast>{feq, d}, dmax, femax, P, fallback);
+      if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, src, dmax, femax, P, fallback);
+      if (fallback) {
+        lam = 0.0;
+        flags |= FLAG_FALLBACK;
+      }
     }
   }
   // The root iteration only reads the mass component of each f^eq_k; rebuilding
   // f^eq from u here (rather than keeping all q*M values live through the
   // iteration) saves registers.  The empty asm makes u opaque so the compiler
-  // recomputes instead of keeping the first copy alive.
+  // recomputes instead of keeping the first copy alive; the rebuilt values are
+  // the same bits.
 #pragma unroll
   for (int m = 0; m < M; ++m) asm volatile("" : "+v"(u[m]));
   Eq<S>::equilibrium(u, feq, P);
@@ -879,10 +1100,81 @@ __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, 
   return lam + 1.0;
 }
 
+// relax_node with a fixed omega known at the call (no root search): the same
+// arithmetic and bits as relax_node's fixed mode, without rebuilding f^eq.
+template <class S>
+__device__ __forceinline__ void relax_node_fixed(double (&f)[S::Q][S::M], const Phys& P) {
+  constexpr int Q = S::Q, M = S::M;
+  double u[M], feq[Q][M], d[Q][M], dmax;
+  node_split<S>(f, u, feq, d, dmax, P);
+  const double lam = P.omega - 1.0;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[k][m] = feq[k][m] - lam * d[k][m];
+}
+
 template <class S>
 __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags) {
   double unused;
   return relax_node<S>(f, mode, P, flags, unused);
+}
+
+// relax_node for the stage kernel of systems with S::kLdsD: d, the masses of
+// f^eq and the cell velocity go to this thread's LDS slots (LdsSrc) right after
+// node_split, and the root search reads them back one velocity at a time, so
+// that they do not occupy registers through it.  Same arithmetic and bits as
+// relax_node.
+template <class S>
+__device__ __forceinline__ double relax_node_lds(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
+                                                 double& lam_out, double* slot) {
+  constexpr int Q = S::Q, M = S::M;
+  static_assert(S::kEagerTol, "LDS-held d needs the eager stop tolerance");
+  double u[M], femax, dmax;
+  {
+    double feq[Q][M], d[Q][M];
+    node_split<S>(f, u, feq, d, dmax, P);
+    femax = max_abs_feq<S>(feq);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+#pragma unroll
+      for (int m = 0; m < M; ++m) slot[(k * M + m) * kLdsStride] = d[k][m];
+      slot[(Q * M + k) * kLdsStride] = feq[k][0];
+    }
+  }
+  bool fallback = false;
+  double lam = P.omega - 1.0;
+  if (mode != 0) {
+    typename S::Node c;
+    const bool adm = S::prepare(u, c, P);
+    if (!adm) flags |= FLAG_INADMISSIBLE;
+#pragma unroll
+    for (int i = 0; i < Q / 2; ++i) slot[(Q * M + Q + i) * kLdsStride] = c.vel[i];
+    lam = 1.0;
+    if (dmax != 0.0) {
+      fallback = !adm;
+      lam = 0.0;
+      if (adm) lam = entropic_lambda<S>(c, LdsSrc<S>{slot}, dmax, femax, P, fallback);
+      if (fallback) {
+        lam = 0.0;
+        flags |= FLAG_FALLBACK;
+      }
+    }
+  }
+  // f^eq rebuilt from u (made opaque, as in relax_node), d read back after lambda
+#pragma unroll
+  for (int m = 0; m < M; ++m) asm volatile("" : "+v"(u[m]));
+  double feq[Q][M];
+  Eq<S>::equilibrium(u, feq, P);
+  unsigned off = 0;
+  asm volatile("" : "+v"(off) : "v"(lam));
+  const double* q = slot + off;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+#pragma unroll
+    for (int m = 0; m < M; ++m) f[k][m] = feq[k][m] - lam * q[(k * M + m) * kLdsStride];
+  lam_out = fallback ? NAN : lam;
+  return lam + 1.0;
 }
 
 // sum_k J_k^T y_k, J_k = d f_k^eq / du = w I + sigma_k (d phi^{n_k}/du) / (2V).
@@ -972,7 +1264,8 @@ __device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, con
       lam = 1.0;
     } else {
       bool fallback = !adm;
-      lam = adm ? entropic_lambda<S>(c, feq, d, dmax, P, fallback) : 0.0;
+      const double femax = S::kEagerTol ? max_abs_feq<S>(feq) : 0.0;
+      lam = adm ? entropic_lambda<S>(c, RegSrc<S>{feq, d}, dmax, femax, P, fallback) : 0.0;
       if (fallback) {
         lam = 0.0;
         flags |= FLAG_FALLBACK;
