@@ -168,6 +168,7 @@ template <int D> struct Advection {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr bool kEagerTol = false;  // see stop_tol
   static constexpr bool kLdsD = false;
+  static constexpr bool kDot = false;
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
   using Fast = Advection;  // no deferred branch (see ShallowWater::Fast)
@@ -206,6 +207,7 @@ template <int D> struct Burgers {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr bool kEagerTol = false;  // see stop_tol
   static constexpr bool kLdsD = false;
+  static constexpr bool kDot = false;
   static constexpr int M = 1, Q = Lat<D>::Q;
   struct Node { double u; };
   using Fast = Burgers;  // no deferred branch (see ShallowWater::Fast)
@@ -336,6 +338,7 @@ template <int D> struct ShallowWater {
   static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr bool kEagerTol = false;  // see stop_tol
   static constexpr bool kLdsD = false;
+  static constexpr bool kDot = false;
   static constexpr int M = D + 1, Q = Lat<D>::Q;
   // rule: set by the Fast variant's evaluations where Newton alone did not give
   // the branch root (the node is then relaxed again with the branch rule)
@@ -527,6 +530,7 @@ struct Euler2 {
   static constexpr int kStageBlocks = 3;
   static constexpr bool kEagerTol = true;  // see stop_tol
   static constexpr bool kLdsD = true;      // stage kernel keeps d in LDS (relax_node_lds)
+  static constexpr bool kDot = true;       // fsum takes the F' term from bregman_dot
   // cell state: density, velocity, pressure, energy, 1/p and c^2 = gamma p / rho
   struct Node { double rho, vel[2], p, E, ip, cs2; };
   using Fast = Euler2;  // no deferred branch (see ShallowWater::Fast)
@@ -604,7 +608,7 @@ struct Euler2 {
   // The thermal part of B is x_1 [phi(za)/(gamma-1) + phi(zb)], phi(z) = z - log1p(z),
   // and ds = log1p(za) + (gamma-1) log1p(zb).  The entropy variables need
   // beta' = rho'/p' = beta/(1 + za): the one further reciprocal, only for F'.
-  struct VelC { double W, dtn, P0c, qc1, qb0, qb1, cW, Vdtn; };
+  struct VelC { double W, dtn, P0c, qc1, qb0, qb1, cW, Vdtn, Q0; };
   template <int k>
   __device__ static VelC vel_consts(const Node& c, double un, double ut, double d0, double dn_, double dt_, double d3,
                                     const Phys& P) {
@@ -621,10 +625,14 @@ struct Euler2 {
     K.qb1 = sg * K.P0c;
     K.cW = s * igm1 * V2 * K.W;
     K.Vdtn = V * K.dtn;
+    // Q(u) = -|u|^2 d_1/2 + u_n d_n + u_t d_t - d_E (the F' term below)
+    K.Q0 = fma(un, dn_, fma(ut, dt_, fma(-0.5 * d0, un * un + ut * ut, -d3)));
     return K;
   }
   // B_k(t) and (DV) F'-term (v(U_k) - v(u)) . d_k; false outside the convexity domain
-  template <int k, bool DV>
+  // B_k(t); DV: the F' term dvd = (v(U_k) - v(u)) . d_k; DVV: also the difference
+  // v(U_k) - v(u) itself in dv (the adjoint's gradient of omega needs it)
+  template <int k, bool DV, bool DVV = DV>
   __device__ static bool eval(const Node& c, double un, double ut, double f1, double d0, double dn_, double dt_,
                               double d3, const VelC& K, double t, double& B, double& dvd, double* dv, const Phys& P,
                               double zlim, bool& small) {
@@ -656,19 +664,26 @@ struct Euler2 {
     const double du2 = fma(dn, dn, dt * dt);
     B = fma(x1, fma(du2, 0.5 * bet, fma(pa, igm1, pb)), (s * P.inv2V) * bet * dp * dn);
     if (DV) {
-      // entropy-variable difference v(U_k) - v(u)
+      // entropy-variable difference v(U_k) - v(u): with ds = log1p(za) + (gamma-1) log1p(zb),
+      //   v(U_k) - v(u) = (-ds/(gamma-1) - (beta'|u'|^2 - beta|u|^2)/2, beta' u' - beta u, -(beta' - beta)),
+      // so its dot product with d_k is -ds d_1/(gamma-1) + beta' Q(u') - beta Q(u), Q as in vel_consts,
+      // with Q(u') = Q(u) + dQ, dQ = dn (d_n - d_1 (2 u_n + dn)/2) + dt (d_t - d_1 (2 u_t + dt)/2)
       const double ds = (za - pa) + (P.p0 - 1.0) * (zb - pb);
       // F' needs far less than full precision (its errors enter the predicted
       // lambda multiplied by lambda - 1): a once-refined reciprocal
       const double dbet = -bet * za * rcp1(1.0 + za);
-      const double unp = un + dn, utp = ut + dt;
-      const double up2 = fma(unp, unp, utp * utp);
-      const double dkin = fma(dbet, up2, bet * fma(dn, 2.0 * un + dn, dt * (2.0 * ut + dt)));
-      dv[0] = fma(-ds, igm1, -0.5 * dkin);
-      dv[1 + n] = fma(dbet, unp, bet * dn);
-      dv[1 + tt] = fma(dbet, utp, bet * dt);
-      dv[3] = -dbet;
-      dvd = fma(dv[0], d0, fma(dv[1 + n], dn_, fma(dv[1 + tt], dt_, dv[3] * d3)));
+      const double hd0 = -0.5 * d0;
+      const double dQ = fma(dn, fma(hd0, fma(2.0, un, dn), dn_), dt * fma(hd0, fma(2.0, ut, dt), dt_));
+      dvd = fma(-ds, d0 * igm1, fma(dbet, K.Q0 + dQ, bet * dQ));
+      if (DVV) {
+        const double unp = un + dn, utp = ut + dt;
+        const double up2 = fma(unp, unp, utp * utp);
+        const double dkin = fma(dbet, up2, bet * fma(dn, 2.0 * un + dn, dt * (2.0 * ut + dt)));
+        dv[0] = fma(-ds, igm1, -0.5 * dkin);
+        dv[1 + n] = fma(dbet, unp, bet * dn);
+        dv[1 + tt] = fma(dbet, utp, bet * dt);
+        dv[3] = -dbet;
+      }
     }
     // rho' > 0, p' > 0 and the sub-characteristic condition rho' W'^2 > gamma p',
     // i.e. W'^2 > c^2 (1 + za); all conditions evaluated (no short-circuit branches)
@@ -686,18 +701,31 @@ struct Euler2 {
     const double un = c.vel[n], ut = c.vel[tt];
     const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
     double dvd;
-    return eval<k, DV>(c, un, ut, feq[0], d0, dn_, dt_, d3, K, t, B, dvd, dv, P, zlim, small);
+    return eval<k, DV, DV>(c, un, ut, feq[0], d0, dn_, dt_, d3, K, t, B, dvd, dv, P, zlim, small);
+  }
+  // bregman returning the F' term (v(U_k) - v(u)) . d_k itself (fsum's form for this system)
+  template <int k, bool DV>
+  __device__ static bool bregman_dot(const Node& c, const double* feq, const double* d, double t, double& B,
+                                     double& dvd, const Phys& P, double zlim, bool& small) {
+    constexpr int n = Lat<2>::axis(k), tt = 1 - n;
+    double d0 = d[0], dn_ = d[1 + n], dt_ = d[1 + tt], d3 = d[3];
+    asm volatile("" : "+v"(d0), "+v"(dn_), "+v"(dt_), "+v"(d3));
+    const double un = c.vel[n], ut = c.vel[tt];
+    const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
+    double dv[4];
+    return eval<k, DV, false>(c, un, ut, feq[0], d0, dn_, dt_, d3, K, t, B, dvd, dv, P, zlim, small);
   }
   // bregman for values just read from thread-private LDS slots (LdsSrc), the cell
   // velocity (vel) included: no copies, and nothing derived from them is kept
   // from one evaluation to the next
   template <int k, bool DV>
   __device__ static bool bregman_fresh(const Node& c, const double* vel, const double* feq, const double* d, double t,
-                                       double& B, double* dv, const Phys& P, double zlim, bool& small) {
+                                       double& B, double& dvd, const Phys& P, double zlim, bool& small) {
     constexpr int n = Lat<2>::axis(k), tt = 1 - n;
     const VelC K = vel_consts<k>(c, vel[n], vel[tt], d[0], d[1 + n], d[1 + tt], d[3], P);
-    double dvd;
-    return eval<k, DV>(c, vel[n], vel[tt], feq[0], d[0], d[1 + n], d[1 + tt], d[3], K, t, B, dvd, dv, P, zlim, small);
+    double dv[4];
+    return eval<k, DV, false>(c, vel[n], vel[tt], feq[0], d[0], d[1 + n], d[1 + tt], d[3], K, t, B, dvd, dv, P, zlim,
+                              small);
   }
   // The predictor's two samples for velocity k, t = +1 and t = -1 (the skip
   // measure at t = -1 only), from one read of its LDS slots: the per-velocity
@@ -713,18 +741,15 @@ struct Euler2 {
     const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
     double B, dvd, dv[4];
     bool sk;
-    // sums in the order of fsum (component by component), so that the register
-    // path (relax_node) gives the same bits
-    ok1 &= eval<k, true>(c, un, ut, f1, d0, dn_, dt_, d3, K, 1.0, B, dvd, dv, P, -1.0, sk);
+    // the same sums as fsum's, so that the register path (relax_node) gives the same bits
+    ok1 &= eval<k, true, false>(c, un, ut, f1, d0, dn_, dt_, d3, K, 1.0, B, dvd, dv, P, -1.0, sk);
     F1 += B;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) dF1 += dv[m] * d[m];
+    dF1 += dvd;
     asm volatile("" : "+v"(f1), "+v"(d0) : "v"(F1), "v"(dF1));
-    okm &= eval<k, true>(c, un, ut, f1, d0, dn_, dt_, d3, K, -1.0, B, dvd, dv, P, zlim, sk);
+    okm &= eval<k, true, false>(c, un, ut, f1, d0, dn_, dt_, d3, K, -1.0, B, dvd, dv, P, zlim, sk);
     small &= sk;
     Fm += B;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) dFm += dv[m] * d[m];
+    dFm += dvd;
   }
 };
 
@@ -812,20 +837,26 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const Src& src, 
     bool sk;
     bool ok;
     if constexpr (Src::kFresh) {
-      double vel[S::Q / 2];
+      double vel[S::Q / 2], dvd;
       src.template get<k>(t, f1, dk, vel);
-      ok = S::template bregman_fresh<k, DV>(c, vel, &f1, dk, t, B, dv, P, zlim, sk);
+      ok = S::template bregman_fresh<k, DV>(c, vel, &f1, dk, t, B, dvd, P, zlim, sk);
+      if (DV) dF += dvd;
+    } else if constexpr (S::kDot) {
+      double dvd;
+      src.template get<k>(t, f1, dk);
+      ok = S::template bregman_dot<k, DV>(c, &f1, dk, t, B, dvd, P, zlim, sk);
+      if (DV) dF += dvd;
     } else {
       src.template get<k>(t, f1, dk);
       ok = S::template bregman<k, DV>(c, &f1, dk, t, B, dv, P, zlim, sk);
+      if (DV) {
+#pragma unroll
+        for (int m = 0; m < S::M; ++m) dF += dv[m] * dk[m];
+      }
     }
     small &= sk;
     okacc &= ok;
     F += B;
-    if (DV) {
-#pragma unroll
-      for (int m = 0; m < S::M; ++m) dF += dv[m] * dk[m];
-    }
     // Serialise the velocities: the next evaluation waits for this one's sums
     // and for its validity and skip tests, materialised here (left as booleans
     // combined at the end, their comparisons sink there and keep the operands of
