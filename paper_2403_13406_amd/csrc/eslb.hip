@@ -421,6 +421,7 @@ __global__ __launch_bounds__(run_lds_threads<S>()) void k_run_lds(Grid g, Phys P
     }
   }
   unsigned flags = 0;
+  unsigned long long nfall = 0;  // node relaxations of this thread that fell back to omega = 1
   long long o = 0;  // offset of the LDS copy relative to the loaded logical layout
   for (long long step = 0; step < nsteps; ++step) {
     for (int p = 0; p < plan.npass; ++p) {
@@ -442,7 +443,10 @@ __global__ __launch_bounds__(run_lds_threads<S>()) void k_run_lds(Grid g, Phys P
 #pragma unroll
           for (int m = 0; m < M; ++m) f[k][m] = lds[(k * M + m) * ncell + id[k]];
         }
-        relax_node<S>(f, md, Pp, flags);
+        unsigned nf = 0;
+        relax_node<S>(f, md, Pp, nf);
+        flags |= nf;
+        nfall += (nf & FLAG_FALLBACK) ? 1ull : 0ull;
 #pragma unroll
         for (int k = 0; k < Q; ++k)
 #pragma unroll
@@ -478,7 +482,7 @@ __global__ __launch_bounds__(run_lds_threads<S>()) void k_run_lds(Grid g, Phys P
   }
   if (flags) {
     atomicOr(&st->flags, flags);
-    if (flags & FLAG_FALLBACK) atomicAdd(&st->n_fallback, 1ull);
+    if (nfall) atomicAdd(&st->n_fallback, nfall);
   }
 }
 
