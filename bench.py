@@ -17,15 +17,21 @@ One JSON line:
   alu          (when profiles/ holds a VALU counter record of the same sources) the
                same launches against the FP64 vector peak and the VALU issue peak
   cpu_baseline the CPU oracle, single-threaded, on a bounded sample of the workload
-  batch        (default run) a reduced sample of the batched ensemble: one
-               batch run (one stage kernel per pass over all instances) vs the plain
-               per-instance loop, same GPU
-  adjoint      (default run) forward vs forward+adjoint with checkpointing on the
-               1024^2 Euler grid, same GPU
+  c1, c2       (default run) the 1D Burgers run (N = 1024, 17 steps to T = 0.2) and
+               the 1D shallow-water run (N = 2^20, 4000 steps), whole runs timed
+               with HIP events: MLUPS and ms per step
+  batch        (default run) the 512-instance 2D shallow-water ensemble at its full
+               step counts: one batch run (one stage kernel per pass over all
+               instances, graph replays) vs the plain per-instance loop, same GPU
+  adjoint      (default run) the 1024^2 Euler run of 2000 steps, checkpoints every
+               50: forward vs forward+adjoint with the taped and the minimal
+               workspace (peak device memory of each), and the gradient against
+               central differences on the first 8 of the 32 seeded directions
   riemann      (default run) schemes (A), (B), (C) of Sec. 6.3 on the 2D Euler
                four-state Riemann problem to T = 0.25 at 1024^2 and 2048^2, wall
                seconds, with the paper's own (other GPU) times beside them
---workload batch / adjoint run those two comparisons at their full sizes instead;
+--workload batch / adjoint run only those two comparisons (the adjoint one with all 32
+directions);
 --workload aux times init, moments, gather and diagnostics at the 4096^2 Euler size.
 """
 import argparse
@@ -218,7 +224,7 @@ def batch_compare(torch, count, steps_scale, tune=True, seed_base=0):
             progress("batch: %d/%d instances initialised" % (i + 1, count))
     cfg = None
     if tune:
-        cfg, _ = b.autotune(f_batch, trial_steps=1)
+        cfg, _ = b.autotune(f_batch)
         progress("batch: autotuned config %s" % cfg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -245,11 +251,17 @@ def batch_compare(torch, count, steps_scale, tune=True, seed_base=0):
             "steps_scale": steps_scale, "batch_mlups": round(cell_steps / t_batch / 1e6, 2),
             "per_instance_mlups": round(cell_steps / t_plain / 1e6, 2),
             "speedup_vs_per_instance": round(t_plain / t_batch, 3), "bitwise_equal_to_per_instance": same,
-            "autotuned_config": cfg, "batch_s": round(t_batch, 3), "per_instance_s": round(t_plain, 3)}
+            "autotuned_config": cfg, "batch_s": round(t_batch, 3), "per_instance_s": round(t_plain, 3),
+            "ensemble_state_GiB": round(sum(f.numel() for f in f_batch) * 8 / 2 ** 30, 3)}
 
 
-def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
-    """Forward vs forward + hand-written adjoint (checkpointing) for L = 1/2 |U(T) - U_target|^2."""
+def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0, minimal=True):
+    """Forward vs forward + hand-written adjoint (checkpointing) for L = 1/2 |U(T) - U_target|^2.
+
+    Both workspaces of the backward sweep are timed: "taped" (each segment recomputed once, its
+    relaxation inputs kept) when it fits in half of the free device memory, and "minimal" (each
+    segment recomputed twice, one state per step of a segment).  fd_dirs > 0 checks the gradient
+    against central differences on the first fd_dirs of the seeded directions (seed 2)."""
     import numpy as np
 
     from paper_2403_13406_amd import Solver
@@ -265,27 +277,47 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
         uT = time_loop(u0, s, nsteps)
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
+    del uT
     progress("adjoint: forward %d steps %.2f s" % (nsteps, t_fwd))
-    nt = s.adjoint_tape_bytes(nsteps, ckpt)
-    taped = nt <= torch.cuda.mem_get_info()[0] // 2
-    times = []
-    for _ in range(2):  # the first call also allocates the workspace
+
+    def fwd_adj(tape):
         x = u0.clone().requires_grad_(True)
         torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
         t0 = time.perf_counter()
-        L = 0.5 * torch.sum((time_loop(x, s, nsteps, ckpt, tape=taped) - ut) ** 2)
+        L = 0.5 * torch.sum((time_loop(x, s, nsteps, ckpt, tape=tape) - ut) ** 2)
         L.backward()
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        progress("adjoint: forward + adjoint %.2f s" % times[-1])
-    t_adj = times[-1]
-    rec = {"grid": "%dx%d" % (n, n), "steps": nsteps, "ckpt_every": ckpt,
-           "forward_s": round(t_fwd, 3), "forward_plus_adjoint_s": round(t_adj, 3),
-           "first_call_s": round(times[0], 3), "ratio_to_forward": round(t_adj / t_fwd, 3), "taped": taped,
-           "workspace_GiB": round((nt if taped else s.adjoint_workspace_bytes(nsteps, ckpt)) / 2 ** 30, 3)}
+        sec = time.perf_counter() - t0
+        peak = torch.cuda.max_memory_allocated() - base
+        progress("adjoint: forward + adjoint (%s) %.2f s, peak %.2f GiB above the inputs"
+                 % ("taped" if tape else "minimal", sec, peak / 2 ** 30))
+        return x.grad, sec, peak
+
+    rec = {"grid": "%dx%d" % (n, n), "steps": nsteps, "ckpt_every": ckpt, "forward_s": round(t_fwd, 3),
+           "state_GiB": round(s.q * s.M * n * n * 8 / 2 ** 30, 4)}
+    nt = s.adjoint_tape_bytes(nsteps, ckpt)
+    modes = []
+    if nt <= torch.cuda.mem_get_info()[0] // 2:
+        modes.append(("taped", True, nt))
+    if minimal or not modes:
+        modes.append(("minimal", False, s.adjoint_workspace_bytes(nsteps, ckpt)))
+    g = None
+    for i, (name, tape, ws) in enumerate(modes):
+        if i == 0:
+            fwd_adj(tape)     # the first call also allocates the workspace
+        grad, sec, peak = fwd_adj(tape)
+        g = grad if g is None else g
+        rec[name] = {"forward_plus_adjoint_s": round(sec, 3), "ratio_to_forward": round(sec / t_fwd, 3),
+                     "workspace_GiB": round(ws / 2 ** 30, 3), "peak_device_GiB": round(peak / 2 ** 30, 3)}
+        torch.cuda.empty_cache()
+    head = rec[modes[0][0]]
+    rec["forward_plus_adjoint_s"] = head["forward_plus_adjoint_s"]
+    rec["ratio_to_forward"] = head["ratio_to_forward"]
+    rec["taped"] = modes[0][1]
     if fd_dirs:
         rng = np.random.default_rng(w.extra["fd_seed"])
-        g = x.grad
         gnorm = float(torch.linalg.vector_norm(g))
         rel, proj = [], []
         for _ in range(fd_dirs):
@@ -299,13 +331,42 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0):
             rel.append(abs(fd - ad) / abs(fd))
             # |g.d| / (|g| |d|): how much of the gradient the direction sees
             proj.append(abs(ad) / (gnorm * float(torch.linalg.vector_norm(dl))))
-            progress("adjoint: FD direction rel diff %.3e (|g.d|/|g||d| = %.2e)" % (rel[-1], proj[-1]))
-        rec["fd_directions"] = fd_dirs
+            progress("adjoint: FD direction %d rel diff %.3e (|g.d|/|g||d| = %.2e)" % (len(rel), rel[-1], proj[-1]))
+        rec["fd_directions"] = "the first %d of the %d seeded directions (seed %d), eps 1e-6" % (
+            fd_dirs, w.extra["fd_dirs"], w.extra["fd_seed"])
         rec["fd_max_rel_diff"] = max(rel)
         rec["fd_median_rel_diff"] = float(np.median(rel))
         rec["fd_worst_direction_projection"] = proj[int(np.argmax(rel))]
         rec["fd_median_projection"] = float(np.median(proj))
     return rec
+
+
+def single_run(torch, w, reps, warm_steps):
+    """A whole run of a single-instance workload (w.nsteps composed steps from equilibrium), timed with
+    HIP events on the solver's stream; the median over reps runs, each from a fresh initial state."""
+    from paper_2403_13406_amd import Solver
+    s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax=w.relax, param=w.param)
+    u0 = torch.from_numpy(w.initial_state()).cuda()
+    f = s.init_equilibrium(u0)
+    s.step(f, warm_steps)
+    s.sync()
+    times = []
+    for _ in range(reps):
+        s.init_equilibrium(u0, f)      # offsets back to 0
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s.stream)
+        s.step(f, w.nsteps)
+        b.record(s.stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b) / 1e3)
+    assert s.sync() == 0
+    d = s.diagnostics(f)
+    times.sort()
+    t = times[len(times) // 2]
+    return {"workload": "%s_%d" % (w.name, w.nx), "cells": w.cells, "steps": w.nsteps, "runs": reps,
+            "run_s": round(t, 6), "ms_per_step": round(t / w.nsteps * 1e3, 5),
+            "mlups": round(w.cells * w.nsteps / t / 1e6, 2), "finite": d["n_nan"] == 0,
+            "fallbacks": d["n_fallback"]}
 
 
 # wall times of the three schemes of Sec. 6.3 on the paper's GPU (other hardware:
@@ -398,7 +459,8 @@ def main():
                     help="skip the reduced batch/adjoint comparisons and the Riemann-problem scheme timings")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0)
     ap.add_argument("--batch-steps-scale", type=float, default=1.0)
-    ap.add_argument("--fd-dirs", type=int, default=0)
+    ap.add_argument("--fd-dirs", type=int, default=None,
+                    help="finite-difference directions of the adjoint check (default: 8 in the default run, 32 with --workload adjoint)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (got --gpus %d)" % args.gpus,
@@ -422,7 +484,7 @@ def main():
                           "aux": r["kernels"]}), flush=True)
         return
     if args.workload == "adjoint":
-        r = adjoint_compare(torch, 1024, 2000, 50, args.fd_dirs)
+        r = adjoint_compare(torch, 1024, 2000, 50, 32 if args.fd_dirs is None else args.fd_dirs)
         rec = {"metric": METRIC, "value": round(1024 * 1024 * 2000 / r["forward_plus_adjoint_s"] / 1e6, 3),
                "unit": "MLUPS (forward+adjoint)", "n_gpus": 1, "steps": 2000, "warmup": 0, "ms_per_step": None,
                "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -432,10 +494,16 @@ def main():
 
     rec, w = bench_single(args, torch)
     if not args.no_extras and args.workload == "euler2d":
+        from paper_2403_13406_amd import workloads as W
         torch.cuda.empty_cache()
-        rec["batch"] = batch_compare(torch, 48, 0.05)
+        rec["c1"] = single_run(torch, W.burgers1d(), reps=21, warm_steps=17)
+        progress("c1: %s" % rec["c1"])
+        rec["c2"] = single_run(torch, W.sw1d(), reps=1, warm_steps=20)
+        progress("c2: %s" % rec["c2"])
         torch.cuda.empty_cache()
-        rec["adjoint"] = adjoint_compare(torch, 1024, 100, 10)   # reduced: 100 steps, a 24 GiB tape
+        rec["batch"] = batch_compare(torch, 512, 1.0)
+        torch.cuda.empty_cache()
+        rec["adjoint"] = adjoint_compare(torch, 1024, 2000, 50, 8 if args.fd_dirs is None else args.fd_dirs)
         torch.cuda.empty_cache()
         rec["riemann"] = riemann_compare(torch)
     if not args.no_cpu_baseline:

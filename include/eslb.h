@@ -303,11 +303,16 @@ int eslb_batch_sync_status(eslb_batch* batch);
 int eslb_batch_set_config(eslb_batch* batch, int32_t block_x, int32_t block_y, int32_t blocks_per_cu,
                           int32_t steps_per_graph);
 int eslb_batch_get_config(const eslb_batch* batch, int32_t* cfg4);
-/* Autotuner: times every supported configuration on scratch copies of one
- * instance per distinct grid size (trial_steps steps each; allocates and frees
- * the copies) and keeps the fastest; *best_ms (optional) gets its trial time.
- * The caller's states and offsets are not modified. */
-int eslb_batch_autotune(eslb_batch* batch, double* const* f_devs, int32_t trial_steps, double* best_ms);
+/* Autotuner: for every supported configuration, builds the device tables and a
+ * one-step graph once, then times max(replays, 3) graph replays with HIP events
+ * (after one untimed replay) and keeps the configuration with the smallest
+ * replay time; *best_ms (optional) gets that time.  The tuning set is a
+ * systematic sample of at most 64 instances along the ensemble sorted by grid
+ * size (its tile mix follows the ensemble's size distribution), run on scratch
+ * copies that are allocated and freed here; the caller's states and offsets are
+ * not modified.  Errors: ESLB_ERR_INVALID_ARG (NULL batch or states, replays < 1,
+ * no non-NULL state), ESLB_ERR_HIP. */
+int eslb_batch_autotune(eslb_batch* batch, double* const* f_devs, int32_t replays, double* best_ms);
 const char* eslb_batch_last_error(const eslb_batch* batch);
 
 const char* eslb_status_string(int code);

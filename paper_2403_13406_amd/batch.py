@@ -67,7 +67,7 @@ class Batch:
         self._check(self.lib.eslb_batch_get_config(self.h, arr))
         return list(arr)
 
-    def autotune(self, states, trial_steps=2):
+    def autotune(self, states, replays=3):
         ms = ctypes.c_double()
-        self._check(self.lib.eslb_batch_autotune(self.h, self._ptrs(states), int(trial_steps), ctypes.byref(ms)))
+        self._check(self.lib.eslb_batch_autotune(self.h, self._ptrs(states), int(replays), ctypes.byref(ms)))
         return self.config(), ms.value

@@ -19,7 +19,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -502,57 +501,78 @@ int eslb_batch_get_config(const eslb_batch* b, int32_t* cfg) {
   return ESLB_OK;
 }
 
-int eslb_batch_autotune(eslb_batch* b, double* const* f, int32_t trial_steps, double* best_ms) {
-  if (!b || !f || trial_steps < 1) return berr(b, ESLB_ERR_INVALID_ARG, "bad argument to eslb_batch_autotune");
-  // One representative instance per distinct grid size, copied to scratch so the
-  // caller's states are untouched; every candidate runs the same trial.
+int eslb_batch_autotune(eslb_batch* b, double* const* f, int32_t replays, double* best_ms) {
+  if (!b || !f || replays < 1) return berr(b, ESLB_ERR_INVALID_ARG, "bad argument to eslb_batch_autotune");
+  replays = std::max(replays, 3);
+  // Tuning set: a systematic sample of at most kTuneInstances instances taken
+  // along the ensemble sorted by grid size, so the tile mix is in proportion to
+  // the ensemble's size distribution.  They run on scratch copies (the caller's
+  // states and offsets are untouched).
+  constexpr int kTuneInstances = 64;
   const int n = (int)b->probs.size();
+  std::vector<int> by_size;
+  for (int i = 0; i < n; ++i)
+    if (f[i]) by_size.push_back(i);
+  if (by_size.empty()) return berr(b, ESLB_ERR_INVALID_ARG, "no state to tune on");
+  std::stable_sort(by_size.begin(), by_size.end(), [&](int a, int c) {
+    return (long long)b->probs[a].nx * b->probs[a].ny < (long long)b->probs[c].nx * b->probs[c].ny;
+  });
+  const int nsamp = std::min((int)by_size.size(), kTuneInstances);
   std::vector<int> reps;
-  for (int i = 0; i < n; ++i) {
-    bool seen = false;
-    for (int r : reps) seen |= (b->probs[r].nx == b->probs[i].nx && b->probs[r].ny == b->probs[i].ny);
-    if (!seen && f[i]) reps.push_back(i);
-  }
-  if (reps.empty()) return berr(b, ESLB_ERR_INVALID_ARG, "no state to tune on");
-  std::vector<double*> scratch(n, nullptr), orig(n, nullptr);
+  for (int j = 0; j < nsamp; ++j) reps.push_back(by_size[(size_t)j * by_size.size() / nsamp]);
+  std::vector<double*> scratch(n, nullptr);
   int rc = ESLB_OK;
   for (int i : reps) {
-    size_t bytes = (size_t)b->q * b->M * b->probs[i].nx * (size_t)b->probs[i].ny * sizeof(double);
-    rc = bhip(b, hipMalloc(&orig[i], bytes), "autotune scratch");
-    if (rc == ESLB_OK) rc = bhip(b, hipMalloc(&scratch[i], bytes), "autotune scratch");
-    if (rc == ESLB_OK) rc = bhip(b, hipMemcpyAsync(orig[i], f[i], bytes, hipMemcpyDeviceToDevice, b->stream), "copy");
+    const size_t bytes = (size_t)b->q * b->M * b->probs[i].nx * (size_t)b->probs[i].ny * sizeof(double);
+    rc = bhip(b, hipMalloc(&scratch[i], bytes), "autotune scratch");
+    if (rc == ESLB_OK) rc = bhip(b, hipMemcpyAsync(scratch[i], f[i], bytes, hipMemcpyDeviceToDevice, b->stream), "copy");
     if (rc != ESLB_OK) break;
   }
-  std::vector<long long> keep_offs = b->offs;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rc == ESLB_OK) rc = bhip(b, hipEventCreate(&e0), "event");
+  if (rc == ESLB_OK) rc = bhip(b, hipEventCreate(&e1), "event");
+  if (rc == ESLB_OK) rc = bhip(b, hipStreamSynchronize(b->stream), "sync");
+  // every sampled instance stays active through the warm-up and timed replays
   std::vector<long long> steps(n, 0);
-  for (int i : reps) steps[i] = trial_steps;
+  for (int i : reps) steps[i] = replays + 2;
+  const std::vector<int> order = sorted_order(steps, reps);
   double best = 1e300;
   Config best_cfg = b->cfg;
   for (const Config& c : kConfigs) {
     if (rc != ESLB_OK) break;
-    double ms = 0.0;
-    for (int rep = 0; rep < 2 && rc == ESLB_OK; ++rep) {  // the first round warms up
-      for (int i : reps) {
-        size_t bytes = (size_t)b->q * b->M * b->probs[i].nx * (size_t)b->probs[i].ny * sizeof(double);
-        rc = bhip(b, hipMemcpyAsync(scratch[i], orig[i], bytes, hipMemcpyDeviceToDevice, b->stream), "copy");
-      }
-      if (rc == ESLB_OK) rc = bhip(b, hipStreamSynchronize(b->stream), "sync");
-      b->offs = keep_offs;
-      const auto t0 = std::chrono::steady_clock::now();
-      if (rc == ESLB_OK) rc = run_sorted(b, c, scratch.data(), sorted_order(steps, reps), steps);
-      const auto t1 = std::chrono::steady_clock::now();
-      ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    // tables and a one-step graph once per configuration; only graph replays are timed
+    RunTables T;
+    rc = build_tables(b, c, scratch.data(), order, steps, T);
+    if (rc != ESLB_OK) break;
+    hipGraphExec_t exec = nullptr;
+    rc = capture_steps(b, c, T, 1, &exec);
+    if (rc == ESLB_OK) {
+      hipLaunchKernelGGL(k_batch_reset, dim3((T.nact + 255) / 256), dim3(256), 0, b->cap, T.ctl, T.nact, T.ntiles,
+                         T.inst, T.omod, T.nact);
+      rc = bhip(b, hipGetLastError(), "reset launch");
     }
+    if (rc == ESLB_OK) rc = bhip(b, hipGraphLaunch(exec, b->cap), "graph launch");  // warm-up
+    double ms = 1e300;
+    for (int r = 0; r < replays && rc == ESLB_OK; ++r) {
+      rc = bhip(b, hipEventRecord(e0, b->cap), "event record");
+      if (rc == ESLB_OK) rc = bhip(b, hipGraphLaunch(exec, b->cap), "graph launch");
+      if (rc == ESLB_OK) rc = bhip(b, hipEventRecord(e1, b->cap), "event record");
+      if (rc == ESLB_OK) rc = bhip(b, hipEventSynchronize(e1), "event sync");
+      float t = 0.f;
+      if (rc == ESLB_OK) rc = bhip(b, hipEventElapsedTime(&t, e0, e1), "event time");
+      if (rc == ESLB_OK) ms = std::min(ms, (double)t);
+    }
+    if (rc == ESLB_OK) rc = bhip(b, hipStreamSynchronize(b->cap), "sync");
+    if (exec) (void)hipGraphExecDestroy(exec);
+    T.release();
     if (rc == ESLB_OK && ms < best) {
       best = ms;
       best_cfg = c;
     }
   }
-  b->offs = keep_offs;
-  for (int i : reps) {
-    (void)hipFree(scratch[i]);
-    (void)hipFree(orig[i]);
-  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (int i : reps) (void)hipFree(scratch[i]);
   if (rc != ESLB_OK) return rc;
   b->cfg = best_cfg;
   if (best_ms) *best_ms = best;

@@ -81,7 +81,7 @@ def test_autotune_leaves_states_untouched_and_picks_a_config():
         s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="entropic", param=w.param)
         states.append(s.init_equilibrium(to_gpu(w.initial_state())))
     before = [to_host(f) for f in states]
-    cfg, ms = b.autotune(states, trial_steps=1)
+    cfg, ms = b.autotune(states)
     assert ms > 0 and cfg[0] * cfg[1] in (128, 256)
     for f, g in zip(states, before):
         assert np.array_equal(to_host(f), g)
@@ -108,7 +108,7 @@ def test_batch_at_the_ensemble_sizes():
         s.step(f, n)
         assert s.sync() == 0
         plain.append((to_host(f), s.offsets))
-    b.autotune(states, trial_steps=1)
+    b.autotune(states)
     b.run(states, steps)
     assert b.sync() == 0
     for i in range(len(ws)):
