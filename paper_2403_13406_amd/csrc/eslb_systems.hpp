@@ -69,12 +69,12 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return fma(d, h, s);
 }
 
-// phi(z) = z - log1p(z) for a pair of arguments.  For |z| < 2^-7 (increments
-// near equilibrium) phi(z) = z^2 g(z) with g(z) = sum_j (-1)^j z^j / (j + 2),
-// its Taylor polynomial to z^4 for |z| <= 2^-10.5, otherwise
-// its Chebyshev-economised degree-6 polynomial on [-2^-7, 2^-7]
-// (relative error below 2^-52 in binary64; no cancellation between z and
-// log1p(z)); otherwise z - log1p(z) with log1p_far for both.
+// phi(z) = z - log1p(z) in three tiers, chosen per pair of arguments (the Euler
+// evaluation's za, zb).  For |z| < 2^-7 (increments near equilibrium)
+// phi(z) = z^2 g(z) with g(z) = sum_j (-1)^j z^j / (j + 2): its Taylor polynomial
+// to z^4 for |z| <= 2^-10.5 (phi_taylor4), otherwise its Chebyshev-economised
+// degree-6 polynomial on [-2^-7, 2^-7] (phi_poly; relative error below 2^-52 in
+// binary64; no cancellation between z and log1p(z)); beyond, z - log1p_far(z).
 __device__ __forceinline__ double phi_poly(double z) {
   double g = 0.12501220790442075;
   g = fma(g, z, -0.14286901156622775);
@@ -131,18 +131,28 @@ __device__ __forceinline__ double phi_taylor4(double z) {
   return (z * z) * g;
 }
 
-__device__ __forceinline__ void phi_pair(double za, double zb, double& pa, double& pb) {
-  constexpr double kTaylor = 0x1.6a09e667f3bcdp-11;  // 2^-10.5
-  if ((fabs(za) <= kTaylor) & (fabs(zb) <= kTaylor)) {
-    pa = phi_taylor4(za);
-    pb = phi_taylor4(zb);
-  } else if ((fabs(za) < 0.0078125) & (fabs(zb) < 0.0078125)) {
+// Bound of the Taylor tier of phi (and of the series reciprocal below).
+constexpr double kPhiTaylor = 0x1.6a09e667f3bcdp-11;  // 2^-10.5
+
+// phi for a pair outside the Taylor tier: the economised polynomial for |z| < 2^-7,
+// otherwise z - log1p_far(z)
+__device__ __forceinline__ void phi_pair_wide(double za, double zb, double& pa, double& pb) {
+  if ((fabs(za) < 0.0078125) & (fabs(zb) < 0.0078125)) {
     pa = phi_poly(za);
     pb = phi_poly(zb);
   } else {
     pa = za - log1p_far(za);
     pb = zb - log1p_far(zb);
   }
+}
+
+// 1/(1 + z) for |z| <= 2^-10.5 from its geometric series to z^4 (truncation
+// below |z|^5 < 2^-52 relative)
+__device__ __forceinline__ double recip1p_small(double z) {
+  double r = z - 1.0;
+  r = fma(z, r, 1.0);
+  r = fma(z, r, -1.0);
+  return fma(z, r, 1.0);
 }
 
 // Threshold of the predictor's skip measure (z / m^2, see Euler2 and
@@ -166,7 +176,8 @@ template <> struct Lat<2> {
 // (Example "Linear transport equation", Sec. 1.2.1 and 1.2.2).
 template <int D> struct Advection {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
-  static constexpr bool kEagerTol = false;  // see stop_tol
+  static constexpr bool kTolFromU = false;  // see stop_tol
+  static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
   static constexpr bool kDot = false;
   static constexpr int M = 1, Q = Lat<D>::Q;
@@ -205,7 +216,8 @@ template <int D> struct Advection {
 // c1 = w + beta u / (2V); B = dU^2 (w/2 + beta (3u + 2 dU) / (12V)).
 template <int D> struct Burgers {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
-  static constexpr bool kEagerTol = false;  // see stop_tol
+  static constexpr bool kTolFromU = false;  // see stop_tol
+  static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
   static constexpr bool kDot = false;
   static constexpr int M = 1, Q = Lat<D>::Q;
@@ -336,7 +348,8 @@ template <int D> struct ShallowWaterFast;
 
 template <int D> struct ShallowWater {
   static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
-  static constexpr bool kEagerTol = false;  // see stop_tol
+  static constexpr bool kTolFromU = false;  // see stop_tol
+  static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
   static constexpr bool kDot = false;
   static constexpr int M = D + 1, Q = Lat<D>::Q;
@@ -528,18 +541,24 @@ struct Euler2 {
   // resident 256-thread blocks per CU asked of the stage kernel: three waves per
   // SIMD (168 VGPRs), which the LDS-held d makes room for
   static constexpr int kStageBlocks = 3;
-  static constexpr bool kEagerTol = true;  // see stop_tol
+  static constexpr bool kTolFromU = true;  // see stop_tol
+  static constexpr bool kSweepFinite = true;  // eval leaves the finiteness of B to fsum
   static constexpr bool kLdsD = true;      // stage kernel keeps d in LDS (relax_node_lds)
   static constexpr bool kDot = true;       // fsum takes the F' term from bregman_dot
-  // cell state: density, velocity, pressure, energy, 1/p and c^2 = gamma p / rho
-  struct Node { double rho, vel[2], p, E, ip, cs2; };
+  // cell state: density, velocity, pressure, energy, 1/p, c^2 = gamma p / rho, and the
+  // products the Bregman evaluations use: beta = rho/p, beta/2, beta/(2V), rho/(2V)
+  struct Node { double rho, vel[2], p, E, ip, cs2, bet, hbet, sbet, rV; };
   using Fast = Euler2;  // no deferred branch (see ShallowWater::Fast)
   __device__ static bool pending(const Node&) { return false; }
   __device__ static void flux(const double* u, int j, double* phi, const Phys& P) {
     const double rho = u[0], ir = rcp(rho);
-    const double vx = u[1] * ir, vy = u[2] * ir;
-    const double p = (P.p0 - 1.0) * (u[3] - 0.5 * rho * (vx * vx + vy * vy));
-    const double uj = j == 0 ? vx : vy;
+    const double vel[2] = {u[1] * ir, u[2] * ir};
+    const double p = (P.p0 - 1.0) * (u[3] - 0.5 * rho * (vel[0] * vel[0] + vel[1] * vel[1]));
+    flux_from(u, vel, p, j, phi);
+  }
+  // flux with the velocity and pressure of u given (as prepare and flux form them)
+  __device__ static void flux_from(const double* u, const double* vel, double p, int j, double* phi) {
+    const double uj = vel[j];
     phi[0] = u[1 + j];
     phi[1] = u[1] * uj;
     phi[2] = u[2] * uj;
@@ -555,6 +574,10 @@ struct Euler2 {
     c.p = (P.p0 - 1.0) * (u[3] - 0.5 * u[0] * (c.vel[0] * c.vel[0] + c.vel[1] * c.vel[1]));
     c.ip = rcp(c.p);
     c.cs2 = P.p0 * c.p * ir;
+    c.bet = c.rho * c.ip;
+    c.hbet = 0.5 * c.bet;
+    c.sbet = P.inv2V * c.bet;
+    c.rV = c.rho * P.inv2V;
     return (c.rho > 0.0) && (c.p > 0.0);
   }
   // limit of the skip measure: 2^-8 m^2, m = 1 - c^2/W_min^2 (negative: never skip)
@@ -608,7 +631,7 @@ struct Euler2 {
   // The thermal part of B is x_1 [phi(za)/(gamma-1) + phi(zb)], phi(z) = z - log1p(z),
   // and ds = log1p(za) + (gamma-1) log1p(zb).  The entropy variables need
   // beta' = rho'/p' = beta/(1 + za): the one further reciprocal, only for F'.
-  struct VelC { double W, dtn, P0c, qc1, qb0, qb1, cW, Vdtn, Q0; };
+  struct VelC { double W, gnd, dtn, P0c, qc1, qb0, qb1, cW, Vdtn, Q0, hd0, d0g; };
   template <int k>
   __device__ static VelC vel_consts(const Node& c, double un, double ut, double d0, double dn_, double dt_, double d3,
                                     const Phys& P) {
@@ -617,6 +640,7 @@ struct Euler2 {
     VelC K;
     K.W = P.W0 + s * un;
     const double gnd = dn_ - un * d0;
+    K.gnd = gnd;
     K.dtn = dt_ - ut * d0;
     K.P0c = s * V2 * gnd;
     K.qc1 = -V2 * d3 + V * d0 * (un * un + ut * ut) + K.P0c * (K.W * igm1 + s * un);
@@ -627,6 +651,8 @@ struct Euler2 {
     K.Vdtn = V * K.dtn;
     // Q(u) = -|u|^2 d_1/2 + u_n d_n + u_t d_t - d_E (the F' term below)
     K.Q0 = fma(un, dn_, fma(ut, dt_, fma(-0.5 * d0, un * un + ut * ut, -d3)));
+    K.hd0 = -0.5 * d0;
+    K.d0g = d0 * igm1;
     return K;
   }
   // B_k(t) and (DV) F'-term (v(U_k) - v(u)) . d_k; false outside the convexity domain
@@ -645,49 +671,86 @@ struct Euler2 {
     const double tdtn = t * K.dtn;
     const double qb = fma(-K.cW, x1, fma(t, K.qb1, K.qb0));
     const double qcx = t * fma(K.Vdtn, fma(2.0 * ut, x1, tdtn), K.qc1 * x1);
-    const double disc = fma(qb, qb, -4.0 * P.q0 * qcx);
-    const bool okd = disc > 0.0;
-    const double den = qb + copysign(okd ? sqrt_pos(disc) : 0.0, qb);
-    const double r1 = rcp(x1 * den);
-    const double ix1 = den * r1;  // 1 / x_1
-    const double dn = -2.0 * qcx * r1;
+    // The root continuous from y = 0 of q0 y^2 + qb y + qcx = 0, y = x_1 dn.  Near
+    // equilibrium eps = q0 qcx / qb^2 is small and y = -(qcx/qb) C(eps) with
+    // C(eps) = 2/(1 + sqrt(1 - 4 eps)) = sum_j Cat_j eps^j (Catalan numbers), summed
+    // to eps^5 for |eps| < 2^-11 (truncation below 133 |eps|^6 < 2^-58): one
+    // reciprocal, 1/(x_1 qb), gives 1/qb and 1/x_1.  Otherwise (also where x_1 qb
+    // vanishes: eps is then not finite) the closed form with a square root.  (On
+    // smooth 4096^2 Euler data |eps| stays below 2^-11.)
+    const double aq = P.q0 * qcx;
+    const double r = rcp(x1 * qb);
+    const double iqb = x1 * r;
+    const double eps = aq * (iqb * iqb);
+    double ix1, dn;  // 1/x_1, dn
+    bool okd = true;
+    if (fabs(eps) < 0x1p-11) {
+      double cat = fma(42.0, eps, 14.0);
+      cat = fma(cat, eps, 5.0);
+      cat = fma(cat, eps, 2.0);
+      cat = fma(cat, eps, 1.0);
+      cat = fma(cat, eps, 1.0);
+      ix1 = qb * r;
+      dn = -qcx * r * cat;
+    } else {
+      const double disc = fma(qb, qb, -4.0 * aq);
+      okd = disc > 0.0;
+      const double den = qb + copysign(okd ? sqrt_pos(disc) : 0.0, qb);
+      const double r1 = rcp(x1 * den);
+      ix1 = den * r1;
+      dn = -2.0 * qcx * r1;
+    }
     const double dt = tdtn * ix1;
     const double dp = fma(-s * V2 * x1, dn, t * K.P0c);
     const double Wp = K.W + s * dn;
     const double al = dp * c.ip;
-    const double zb = fma(s * rho * P.inv2V, dn, -e1) * ix1;
+    const double zb = fma(s * c.rV, dn, -e1) * ix1;
     const double za = fma(al, zb, al + zb);
     small = (fabs(za) <= zlim) & (fabs(zb) <= zlim) & (fabs(e1) <= zlim * f1);
-    double pa, pb;
-    phi_pair(za, zb, pa, pb);
-    const double bet = rho * c.ip;
+    // phi(za), phi(zb), (DV) 1/(1 + za) = beta'/beta, and the domain conditions
+    // rho' > 0 (zb > -1; with W' > 0, also x_1 > 0) and p' > 0 (al > -1).  In the
+    // Taylor tier (|za|, |zb| <= 2^-10.5) rho'/rho and p'/p are within 2^-10 of 1,
+    // so those conditions hold and are not tested.
+    double pa, pb, ira = 0.0;
+    bool okx;
+    if ((fabs(za) <= kPhiTaylor) & (fabs(zb) <= kPhiTaylor)) {
+      pa = phi_taylor4(za);
+      pb = phi_taylor4(zb);
+      if (DV) ira = recip1p_small(za);
+      okx = okd;
+    } else {
+      phi_pair_wide(za, zb, pa, pb);
+      // F' needs far less than full precision (its errors enter the predicted
+      // lambda multiplied by lambda - 1): a once-refined reciprocal
+      if (DV) ira = rcp1(1.0 + za);
+      okx = okd & (x1 > 0.0) & (zb > -1.0) & (al > -1.0);
+    }
     const double du2 = fma(dn, dn, dt * dt);
-    B = fma(x1, fma(du2, 0.5 * bet, fma(pa, igm1, pb)), (s * P.inv2V) * bet * dp * dn);
+    B = fma(x1, fma(du2, c.hbet, fma(pa, igm1, pb)), (s * c.sbet) * dp * dn);
     if (DV) {
       // entropy-variable difference v(U_k) - v(u): with ds = log1p(za) + (gamma-1) log1p(zb),
       //   v(U_k) - v(u) = (-ds/(gamma-1) - (beta'|u'|^2 - beta|u|^2)/2, beta' u' - beta u, -(beta' - beta)),
       // so its dot product with d_k is -ds d_1/(gamma-1) + beta' Q(u') - beta Q(u), Q as in vel_consts,
-      // with Q(u') = Q(u) + dQ, dQ = dn (d_n - d_1 (2 u_n + dn)/2) + dt (d_t - d_1 (2 u_t + dt)/2)
+      // with Q(u') = Q(u) + dQ, dQ = dn (d_n - u_n d_1) + dt (d_t - u_t d_1) - |du|^2 d_1/2
+      // and beta' Q(u') - beta Q(u) = beta (dQ - za Q(u)) / (1 + za)
       const double ds = (za - pa) + (P.p0 - 1.0) * (zb - pb);
-      // F' needs far less than full precision (its errors enter the predicted
-      // lambda multiplied by lambda - 1): a once-refined reciprocal
-      const double dbet = -bet * za * rcp1(1.0 + za);
-      const double hd0 = -0.5 * d0;
-      const double dQ = fma(dn, fma(hd0, fma(2.0, un, dn), dn_), dt * fma(hd0, fma(2.0, ut, dt), dt_));
-      dvd = fma(-ds, d0 * igm1, fma(dbet, K.Q0 + dQ, bet * dQ));
+      const double dQ = fma(K.hd0, du2, fma(dn, K.gnd, dt * K.dtn));
+      dvd = fma(-ds, K.d0g, (c.bet * ira) * fma(-za, K.Q0, dQ));
       if (DVV) {
+        const double dbet = -c.bet * za * ira;
         const double unp = un + dn, utp = ut + dt;
         const double up2 = fma(unp, unp, utp * utp);
-        const double dkin = fma(dbet, up2, bet * fma(dn, 2.0 * un + dn, dt * (2.0 * ut + dt)));
+        const double dkin = fma(dbet, up2, c.bet * fma(dn, 2.0 * un + dn, dt * (2.0 * ut + dt)));
         dv[0] = fma(-ds, igm1, -0.5 * dkin);
-        dv[1 + n] = fma(dbet, unp, bet * dn);
-        dv[1 + tt] = fma(dbet, utp, bet * dt);
+        dv[1 + n] = fma(dbet, unp, c.bet * dn);
+        dv[1 + tt] = fma(dbet, utp, c.bet * dt);
         dv[3] = -dbet;
       }
     }
-    // rho' > 0, p' > 0 and the sub-characteristic condition rho' W'^2 > gamma p',
-    // i.e. W'^2 > c^2 (1 + za); all conditions evaluated (no short-circuit branches)
-    return okd & (x1 > 0.0) & (Wp > 0.0) & (zb > -1.0) & (al > -1.0) & (Wp * Wp > c.cs2 * (1.0 + za)) & isfinite(B);
+    // W' > 0 and the sub-characteristic condition rho' W'^2 > gamma p', i.e.
+    // W'^2 > c^2 (1 + za), as one test: W'|W'| > c^2 (1 + za) (1 + za > 0 where okx
+    // holds).  A non-finite B is caught on the sum F by the sweeps (fsum, fsum_pm).
+    return okx & (Wp * fabs(Wp) > fma(c.cs2, za, c.cs2));
   }
   template <int k, bool DV>
   __device__ static bool bregman(const Node& c, const double* feq, const double* d, double t, double& B, double* dv,
@@ -743,13 +806,13 @@ struct Euler2 {
     bool sk;
     // the same sums as fsum's, so that the register path (relax_node) gives the same bits
     ok1 &= eval<k, true, false>(c, un, ut, f1, d0, dn_, dt_, d3, K, 1.0, B, dvd, dv, P, -1.0, sk);
-    F1 += B;
-    dF1 += dvd;
+    F1 = (k == 0) ? B : F1 + B;  // the callers start the sums at 0
+    dF1 = (k == 0) ? dvd : dF1 + dvd;
     asm volatile("" : "+v"(f1), "+v"(d0) : "v"(F1), "v"(dF1));
     okm &= eval<k, true, false>(c, un, ut, f1, d0, dn_, dt_, d3, K, -1.0, B, dvd, dv, P, zlim, sk);
     small &= sk;
-    Fm += B;
-    dFm += dvd;
+    Fm = (k == 0) ? B : Fm + B;
+    dFm = (k == 0) ? dvd : dFm + dvd;
   }
 };
 
@@ -765,12 +828,41 @@ template <class S> struct Eq {
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
       const int ax = (Q == 4) ? (k & 1) : 0;
-      const double s = (k < Q / 2) ? P.inv2V : -P.inv2V;
 #pragma unroll
-      for (int m = 0; m < M; ++m) feq[k][m] = P.w * u[m] + s * (ax == 0 ? phx[m] : phy[m]);
+      for (int m = 0; m < M; ++m) feq[k][m] = component(u[m], ax == 0 ? phx[m] : phy[m], k, P);
     }
   }
+  // equilibrium from u with its velocity and pressure given (S::flux_from; the same
+  // bits as equilibrium(u) when vel and p are the values prepare forms from u)
+  __device__ static void equilibrium_from(const double* u, const double* vel, double p, double (&feq)[Q][M],
+                                          const Phys& P) {
+    double phx[M], phy[M];
+    S::flux_from(u, vel, p, 0, phx);
+    if (Q == 4) S::flux_from(u, vel, p, 1, phy);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      const int ax = (Q == 4) ? (k & 1) : 0;
+#pragma unroll
+      for (int m = 0; m < M; ++m) feq[k][m] = component(u[m], ax == 0 ? phx[m] : phy[m], k, P);
+    }
+  }
+  // f^eq_{k,m} from u_m and phi^{n_k}_m (the same bits wherever it is formed)
+  __device__ static double component(double um, double phim, int k, const Phys& P) {
+    const double s = (k < Q / 2) ? P.inv2V : -P.inv2V;
+    return P.w * um + s * phim;
+  }
 };
+
+// max |d| over an array (a maximum of computed values)
+template <class S>
+__device__ __forceinline__ double max_abs(const double (&d)[S::Q][S::M]) {
+  double m = 0.0;
+#pragma unroll
+  for (int k = 0; k < S::Q; ++k)
+#pragma unroll
+    for (int j = 0; j < S::M; ++j) m = fmax(m, fabs(d[k][j]));
+  return m;
+}
 
 // Where the root search reads d_k and the mass component of f^eq_k (the only
 // component of f^eq the Bregman terms use): the arrays of node_split (RegSrc),
@@ -788,39 +880,43 @@ template <class S> struct RegSrc {
 #pragma unroll
     for (int m = 0; m < S::M; ++m) dk[m] = d[k][m];
   }
-  __device__ __forceinline__ double max_abs_feq() const {
-    double femax = 0.0;
-#pragma unroll
-    for (int k = 0; k < S::Q; ++k)
-#pragma unroll
-      for (int m = 0; m < S::M; ++m) femax = fmax(femax, fabs(feq[k][m]));
-    return femax;
-  }
+  __device__ __forceinline__ double max_abs_feq() const { return max_abs<S>(feq); }
+  __device__ __forceinline__ double dmax() const { return max_abs<S>(d); }
 };
 
 // LDS slots of one thread: slot j at p[j * kLdsStride] (blocks of kLdsStride
 // threads, one slot of each thread side by side: conflict-free, and every slot
-// an immediate offset from one address).  d_{k,m} at j = k M + m, the mass of
-// f^eq_k at j = Q M + k, the cell velocity at j = Q M + Q + i (i < Q/2, the dimension).
+// an immediate offset from one address).  d_{k,m} at j = k M + m, the cell
+// velocity at j = Q M + i (i < Q/2, the dimension).  18 slots for D2Q4^4: 18 KiB
+// per 128-thread block, so eight blocks (four waves per SIMD) fit in a CU's LDS.
 constexpr int kLdsStride = 128;
 template <class S>
-__host__ __device__ constexpr int lds_slots() { return S::Q * S::M + S::Q + S::Q / 2; }
+__host__ __device__ constexpr int lds_slots() { return S::Q * S::M + S::Q / 2; }
 
 template <class S> struct LdsSrc {
   static constexpr bool kFresh = true;  // every get is a fresh read: S::bregman_fresh, no copies
   double* p;
+  const double (&u)[S::M];  // the cell's conserved moments (registers)
+  const Phys& P;
   template <int k>
   __device__ __forceinline__ void get(double fence, double& f1, double (&dk)[S::M], double (&vel)[S::Q / 2]) const {
     unsigned off = 0;
     asm volatile("" : "+v"(off) : "v"(fence));
     const double* q = p + off;
-    f1 = q[(S::Q * S::M + k) * kLdsStride];
+    // the mass of f^eq_k from u (phi^{n_k}_0 is the momentum u_{1+n_k}), as node_split forms it
+    f1 = Eq<S>::component(u[0], u[1 + Lat<S::D>::axis(k)], k, P);
 #pragma unroll
     for (int m = 0; m < S::M; ++m) dk[m] = q[(k * S::M + m) * kLdsStride];
 #pragma unroll
-    for (int i = 0; i < S::Q / 2; ++i) vel[i] = q[(S::Q * S::M + S::Q + i) * kLdsStride];
+    for (int i = 0; i < S::Q / 2; ++i) vel[i] = q[(S::Q * S::M + i) * kLdsStride];
   }
-  __device__ __forceinline__ double max_abs_feq() const { return 0.0; }  // eager-tolerance systems only
+  __device__ __forceinline__ double max_abs_feq() const { return 0.0; }  // S::kTolFromU systems only
+  __device__ __forceinline__ double dmax() const {
+    double m = 0.0;
+#pragma unroll
+    for (int j = 0; j < S::Q * S::M; ++j) m = fmax(m, fabs(p[j * kLdsStride]));
+    return m;
+  }
 };
 
 // F(t) = sum_k B_k and (DV) F'(t) = sum_k (v(U_k) - v(u)) . d_k, velocities k..Q-1.
@@ -831,6 +927,7 @@ template <class S, bool DV = true, int k = 0, class Src>
 __device__ __forceinline__ bool fsum(const typename S::Node& c, const Src& src, double t, double& F, double& dF,
                                      const Phys& P, double zlim, bool& small, bool okacc = true) {
   if constexpr (k == S::Q) {
+    if constexpr (S::kSweepFinite) return okacc & isfinite(F);
     return okacc;
   } else {
     double dv[S::M], B, f1, dk[S::M];
@@ -840,12 +937,12 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const Src& src, 
       double vel[S::Q / 2], dvd;
       src.template get<k>(t, f1, dk, vel);
       ok = S::template bregman_fresh<k, DV>(c, vel, &f1, dk, t, B, dvd, P, zlim, sk);
-      if (DV) dF += dvd;
+      if (DV) dF = (k == 0) ? dvd : dF + dvd;  // the callers start the sums at 0
     } else if constexpr (S::kDot) {
       double dvd;
       src.template get<k>(t, f1, dk);
       ok = S::template bregman_dot<k, DV>(c, &f1, dk, t, B, dvd, P, zlim, sk);
-      if (DV) dF += dvd;
+      if (DV) dF = (k == 0) ? dvd : dF + dvd;
     } else {
       src.template get<k>(t, f1, dk);
       ok = S::template bregman<k, DV>(c, &f1, dk, t, B, dv, P, zlim, sk);
@@ -856,7 +953,11 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const Src& src, 
     }
     small &= sk;
     okacc &= ok;
-    F += B;
+    if constexpr (S::kDot) {
+      F = (k == 0) ? B : F + B;
+    } else {
+      F += B;
+    }
     // Serialise the velocities: the next evaluation waits for this one's sums
     // and for its validity and skip tests, materialised here (left as booleans
     // combined at the end, their comparisons sink there and keep the operands of
@@ -901,11 +1002,12 @@ __device__ __forceinline__ bool fsum(const typename S::Node& c, const double (&f
   return fsum<S, DV, 0>(c, RegSrc<S>{feq, d}, t, F, dF, P, zlim, small);
 }
 
-// u = sum_k f_k, f^eq(u), d = f - f^eq and dmax = max |d| (a maximum of
-// computed values: no NaN canonicalisation, which one over the loaded f would need).
+// u = sum_k f_k, f^eq(u), d = f - f^eq and nz = (some |d_{k,m}| > 0, i.e. max |d| > 0
+// with NaN entries ignored as fmax ignores them).  max |d| itself is formed only
+// where the root search needs it (Src::dmax).
 template <class S>
 __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double (&u)[S::M],
-                                           double (&feq)[S::Q][S::M], double (&d)[S::Q][S::M], double& dmax,
+                                           double (&feq)[S::Q][S::M], double (&d)[S::Q][S::M], bool& nz,
                                            const Phys& P) {
   constexpr int Q = S::Q, M = S::M;
 #pragma unroll
@@ -916,28 +1018,39 @@ __device__ __forceinline__ void node_split(const double (&f)[S::Q][S::M], double
     u[m] = acc;
   }
   Eq<S>::equilibrium(u, feq, P);
-  dmax = 0.0;
+  nz = false;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
 #pragma unroll
     for (int m = 0; m < M; ++m) {
       d[k][m] = f[k][m] - feq[k][m];
-      dmax = fmax(dmax, fabs(d[k][m]));
+      nz |= fabs(d[k][m]) > 0.0;
     }
 }
 
+
 // Tolerance of the stop rule: 2 eps (max |f^eq| + dmax), max |f^eq| + dmax being an
 // upper bound of max(|f^eq|, |f|) within a factor 2.  Only the paths past the
-// predictor shortcut need it, so by default it is formed there from the f^eq of
-// node_split (S::kEagerTol: formed at once instead, so that only the mass
-// components of f^eq stay live through the root search).
-template <class S>
-__device__ __forceinline__ double max_abs_feq(const double (&feq)[S::Q][S::M]) {
-  return RegSrc<S>{feq, feq}.max_abs_feq();
-}
+// predictor shortcut need it, so it is formed there: from the f^eq of node_split
+// (held by the source), or (S::kTolFromU) from f^eq rebuilt from the cell's u,
+// so that only the mass components of f^eq stay live through the root search.
+// The rebuild works on an opaque copy of u, so that the compiler cannot reuse
+// (and keep live) node_split's f^eq instead; it gives the same bits.
 template <class S, class Src>
-__device__ __forceinline__ double stop_tol(const Src& src, double dmax, double femax) {
-  if constexpr (!S::kEagerTol) femax = src.max_abs_feq();
+__device__ __forceinline__ double stop_tol(const Src& src, double dmax, const double (&u)[S::M], const Phys& P) {
+  double femax;
+  if constexpr (S::kTolFromU) {
+    double uu[S::M], feq[S::Q][S::M];
+#pragma unroll
+    for (int m = 0; m < S::M; ++m) {
+      uu[m] = u[m];
+      asm volatile("" : "+v"(uu[m]));
+    }
+    Eq<S>::equilibrium(uu, feq, P);
+    femax = max_abs<S>(feq);
+  } else {
+    femax = src.max_abs_feq();
+  }
   return 2.0 * 2.220446049250313e-16 * (femax + dmax);
 }
 
@@ -952,7 +1065,7 @@ __device__ __forceinline__ double stop_tol(const Src& src, double dmax, double f
 // bisection bracket takes over.  fallback = true when no root lies inside the
 // convexity domain (omega = 1 then).
 template <class S, class Src>
-__device__ inline double entropic_lambda(const typename S::Node& c, const Src& src, double dmax, double femax,
+__device__ inline double entropic_lambda(const typename S::Node& c, const Src& src, const double (&u)[S::M],
                                          const Phys& P, bool& fallback) {
   fallback = false;
   double F1 = 0.0, dF1 = 0.0;
@@ -964,6 +1077,10 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
     // both samples in one sweep; the t = -1 one is discarded where t = +1 is outside the domain
     bool ok1 = true;
     fsum_pm<S>(c, src, P, S::skip_limit(c, P), F1, dF1, ok1, Fm, dFm, okm, small);
+    if constexpr (S::kSweepFinite) {
+      ok1 &= isfinite(F1);
+      okm &= isfinite(Fm);
+    }
     if (!ok1) {
       fallback = !S::pending(c);
       return 0.0;
@@ -1004,9 +1121,11 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
       // three steps leave it below 2^-55 wherever |lambda - 1| < 2^-6 (the
       // predictor's skip region and far beyond); a fourth is taken where the third
       // step was not already below 2^-26.  The reciprocals need no more than 2^-48.
-      double lp = 1.0, pd = 1.0, rpd = 1.0, st = 0.0;
+      // The first step is xn: at lambda = 1 the model takes G(-1) = Fm and its
+      // derivative -G'(-1), so the step is 1 + (Fm - F1)/F'(-1).
+      double lp = xn, pd = 1.0, rpd = 1.0, st = 0.0;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
+      for (int j = 0; j < 2; ++j) {
         const double g = aa + lp * (-bb + lp * (cc - dd * lp));
         const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
         const double pv = lp * lp * g - G1;
@@ -1027,7 +1146,8 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
         // close to equilibrium the prediction is within the stopping tolerance
         if (small) return lp;
         double F3 = 0.0, dF3 = 0.0;
-        const double tol = stop_tol<S>(src, dmax, femax);
+        const double dmax = src.dmax();
+        const double tol = stop_tol<S>(src, dmax, u, P);
         const bool ok3 = fsum<S, false>(c, src, -lp, F3, dF3, P, -1.0, unused);
         if (S::pending(c)) return 0.0;
         const double H3 = F3 - F1;
@@ -1043,7 +1163,8 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
     }
     x = (isfinite(xn) && xn > lo && xn < hi) ? xn : (isinf(hi) ? 2.0 : 0.5 * (lo + hi));
   }
-  const double tol = stop_tol<S>(src, dmax, femax);
+  const double dmax = src.dmax();
+  const double tol = stop_tol<S>(src, dmax, u, P);
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double F = 0.0, dF = 0.0;
@@ -1088,8 +1209,9 @@ template <class S>
 __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
                                     double& lam_out) {
   constexpr int Q = S::Q, M = S::M;
-  double u[M], feq[Q][M], d[Q][M], dmax;
-  node_split<S>(f, u, feq, d, dmax, P);
+  double u[M], feq[Q][M], d[Q][M];
+  bool nz;
+  node_split<S>(f, u, feq, d, nz, P);
   // Both modes end with the same update f' = f^eq - lambda d, lambda = omega - 1
   // (for fixed omega, (1 - omega) f + omega f^eq written in d = f - f^eq): no
   // branch of the fixed mode keeps f or f^eq live through the entropic root search.
@@ -1102,13 +1224,12 @@ __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, 
     // At equilibrium (d = 0, so f = f^eq exactly) omega = 2, the limit of the
     // root; the common update below then returns f^eq = f.
     lam = 1.0;
-    if (dmax != 0.0) {
+    if (nz) {
       fallback = !adm;
       lam = 0.0;
-      const double femax = S::kEagerTol ? max_abs_feq<S>(feq) : 0.0;
       const RegSrc<S> src{feq, d};
-      if (adm) lam = entropic_lambda<typename S::Fast>(c, RegSrc<typename S::Fast>{feq, d}, dmax, femax, P, fallback);
-      if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, src, dmax, femax, P, fallback);
+      if (adm) lam = entropic_lambda<typename S::Fast>(c, RegSrc<typename S::Fast>{feq, d}, u, P, fallback);
+      if (S::Fast::pending(c)) lam = entropic_lambda<S>(c, src, u, P, fallback);
       if (fallback) {
         lam = 0.0;
         flags |= FLAG_FALLBACK;
@@ -1136,8 +1257,9 @@ __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, 
 template <class S>
 __device__ __forceinline__ void relax_node_fixed(double (&f)[S::Q][S::M], const Phys& P) {
   constexpr int Q = S::Q, M = S::M;
-  double u[M], feq[Q][M], d[Q][M], dmax;
-  node_split<S>(f, u, feq, d, dmax, P);
+  double u[M], feq[Q][M], d[Q][M];
+  bool nz;
+  node_split<S>(f, u, feq, d, nz, P);
   const double lam = P.omega - 1.0;
 #pragma unroll
   for (int k = 0; k < Q; ++k)
@@ -1151,52 +1273,60 @@ __device__ __forceinline__ double relax_node(double (&f)[S::Q][S::M], int mode, 
   return relax_node<S>(f, mode, P, flags, unused);
 }
 
-// relax_node for the stage kernel of systems with S::kLdsD: d, the masses of
-// f^eq and the cell velocity go to this thread's LDS slots (LdsSrc) right after
-// node_split, and the root search reads them back one velocity at a time, so
-// that they do not occupy registers through it.  Same arithmetic and bits as
-// relax_node.
+// relax_node for the stage kernel of systems with S::kLdsD: d and the cell
+// velocity go to this thread's LDS slots (LdsSrc) right after node_split, and the
+// root search reads them back one velocity at a time (the masses of f^eq it forms
+// again from u), so that they do not occupy registers through it.  Same
+// arithmetic and bits as relax_node.
 template <class S>
 __device__ __forceinline__ double relax_node_lds(double (&f)[S::Q][S::M], int mode, const Phys& P, unsigned& flags,
                                                  double& lam_out, double* slot) {
   constexpr int Q = S::Q, M = S::M;
-  static_assert(S::kEagerTol, "LDS-held d needs the eager stop tolerance");
-  double u[M], femax, dmax;
+  static_assert(S::kTolFromU, "LDS-held d needs the stop tolerance from u");
+  double u[M];
+  bool nz;
   {
     double feq[Q][M], d[Q][M];
-    node_split<S>(f, u, feq, d, dmax, P);
-    femax = max_abs_feq<S>(feq);
+    node_split<S>(f, u, feq, d, nz, P);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
 #pragma unroll
       for (int m = 0; m < M; ++m) slot[(k * M + m) * kLdsStride] = d[k][m];
-      slot[(Q * M + k) * kLdsStride] = feq[k][0];
     }
   }
   bool fallback = false;
   double lam = P.omega - 1.0;
+  typename S::Node c;
+  const bool adm = S::prepare(u, c, P);
   if (mode != 0) {
-    typename S::Node c;
-    const bool adm = S::prepare(u, c, P);
     if (!adm) flags |= FLAG_INADMISSIBLE;
 #pragma unroll
-    for (int i = 0; i < Q / 2; ++i) slot[(Q * M + Q + i) * kLdsStride] = c.vel[i];
+    for (int i = 0; i < Q / 2; ++i) slot[(Q * M + i) * kLdsStride] = c.vel[i];
     lam = 1.0;
-    if (dmax != 0.0) {
+    if (nz) {
       fallback = !adm;
       lam = 0.0;
-      if (adm) lam = entropic_lambda<S>(c, LdsSrc<S>{slot}, dmax, femax, P, fallback);
+      if (adm) lam = entropic_lambda<S>(c, LdsSrc<S>{slot, u, P}, u, P, fallback);
       if (fallback) {
         lam = 0.0;
         flags |= FLAG_FALLBACK;
       }
     }
   }
-  // f^eq rebuilt from u (made opaque, as in relax_node), d read back after lambda
+  // f^eq rebuilt from u with the velocity and pressure of prepare (the same bits
+  // as node_split's; made opaque, as in relax_node, so that the compiler forms it
+  // again instead of keeping node_split's live), d read back after lambda
+  double vel[Q / 2], pc = c.p;
+#pragma unroll
+  for (int i = 0; i < Q / 2; ++i) {
+    vel[i] = c.vel[i];
+    asm volatile("" : "+v"(vel[i]));
+  }
+  asm volatile("" : "+v"(pc));
 #pragma unroll
   for (int m = 0; m < M; ++m) asm volatile("" : "+v"(u[m]));
   double feq[Q][M];
-  Eq<S>::equilibrium(u, feq, P);
+  Eq<S>::equilibrium_from(u, vel, pc, feq, P);
   unsigned off = 0;
   asm volatile("" : "+v"(off) : "v"(lam));
   const double* q = slot + off;
@@ -1282,8 +1412,9 @@ __device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, con
                                     double (&u)[S::M], double (&d)[S::Q][S::M], double& lam, double& om,
                                     bool& grad) {
   constexpr int Q = S::Q, M = S::M;
-  double feq[Q][M], dmax;
-  node_split<S>(h, u, feq, d, dmax, P);
+  double feq[Q][M];
+  bool nz;
+  node_split<S>(h, u, feq, d, nz, P);
   typename S::Node c;
   const bool adm = S::prepare(u, c, P);
   om = P.omega;
@@ -1291,12 +1422,11 @@ __device__ inline void adjoint_root(const double (&h)[S::Q][S::M], int mode, con
   grad = false;
   if (mode == 1) {
     if (!adm) flags |= FLAG_INADMISSIBLE;
-    if (dmax == 0.0) {
+    if (!nz) {
       lam = 1.0;
     } else {
       bool fallback = !adm;
-      const double femax = S::kEagerTol ? max_abs_feq<S>(feq) : 0.0;
-      lam = adm ? entropic_lambda<S>(c, RegSrc<S>{feq, d}, dmax, femax, P, fallback) : 0.0;
+      lam = adm ? entropic_lambda<S>(c, RegSrc<S>{feq, d}, u, P, fallback) : 0.0;
       if (fallback) {
         lam = 0.0;
         flags |= FLAG_FALLBACK;
@@ -1314,15 +1444,16 @@ __device__ inline void adjoint_taped(const double (&h)[S::Q][S::M], int mode, do
                                      double (&u)[S::M], double (&d)[S::Q][S::M], double& lam, double& om,
                                      bool& grad) {
   constexpr int Q = S::Q, M = S::M;
-  double feq[Q][M], dmax;
-  node_split<S>(h, u, feq, d, dmax, P);
+  double feq[Q][M];
+  bool nz;
+  node_split<S>(h, u, feq, d, nz, P);
   om = P.omega;
   lam = P.omega - 1.0;
   grad = false;
   if (mode == 1) {
     const bool fallback = isnan(lam_rec);
     lam = fallback ? 0.0 : lam_rec;
-    grad = !fallback && (dmax != 0.0);
+    grad = !fallback && nz;
     om = lam + 1.0;
   }
 }
