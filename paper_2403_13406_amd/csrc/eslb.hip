@@ -164,6 +164,11 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
         double lam;
         om = stage_relax<S>(f, mode, P, flags, lam);
       }
+      // the offsets enter the stores as 32-bit values of this block, so that each
+      // store takes the scalar-base + 32-bit-offset form (carried across the root
+      // search, they become 64-bit addresses and one 64-bit add per store)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) asm volatile("" : "+v"(off[k]));
 #pragma unroll
       for (int k = 0; k < Q; ++k)
 #pragma unroll
