@@ -674,8 +674,11 @@ struct Euler2 {
     // The root continuous from y = 0 of q0 y^2 + qb y + qcx = 0, y = x_1 dn.  Near
     // equilibrium eps = q0 qcx / qb^2 is small and y = -(qcx/qb) C(eps) with
     // C(eps) = 2/(1 + sqrt(1 - 4 eps)) = sum_j Cat_j eps^j (Catalan numbers), summed
-    // to eps^5 for |eps| < 2^-11 (truncation below 133 |eps|^6 < 2^-58): one
-    // reciprocal, 1/(x_1 qb), gives 1/qb and 1/x_1.  Otherwise (also where x_1 qb
+    // to eps^4 for |eps| < 2^-11 (truncation below 43 |eps|^5 < 2^-49): one
+    // reciprocal, 1/(x_1 qb), gives 1/qb and 1/x_1.  B needs no more: it is formed
+    // from the increments with nothing O(1) cancelling, so a relative error e of dn
+    // moves F by about 2e relative, and lambda by about e; near equilibrium
+    // (|d| <= 2^-11 |f| here) that moves f^eq - lambda d by e |d|, below rounding.  Otherwise (also where x_1 qb
     // vanishes: eps is then not finite) the closed form with a square root.  (On
     // smooth 4096^2 Euler data |eps| stays below 2^-11.)
     const double aq = P.q0 * qcx;
@@ -685,8 +688,7 @@ struct Euler2 {
     double ix1, dn;  // 1/x_1, dn
     bool okd = true;
     if (fabs(eps) < 0x1p-11) {
-      double cat = fma(42.0, eps, 14.0);
-      cat = fma(cat, eps, 5.0);
+      double cat = fma(14.0, eps, 5.0);
       cat = fma(cat, eps, 2.0);
       cat = fma(cat, eps, 1.0);
       cat = fma(cat, eps, 1.0);
@@ -1119,8 +1121,11 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
       // within |lambda - 1| of 1, and its second derivative over twice its first is
       // about 1/2, so the error after j steps is about 2 (|lambda - 1| / 2)^(2^j):
       // three steps leave it below 2^-55 wherever |lambda - 1| < 2^-6 (the
-      // predictor's skip region and far beyond); a fourth is taken where the third
-      // step was not already below 2^-26.  The reciprocals need no more than 2^-48.
+      // predictor's skip region and far beyond); the third is taken only where the
+      // second was not already below 2^-26, or, where the prediction is taken as
+      // the root (small), below 2^-22: the error after it is then below 2^-45, and
+      // the update moves f^eq - lambda d by that times |d| <= 2^-8 |f| about (the
+      // skip region): below rounding.  The reciprocals need no more than 2^-48.
       // The first step is xn: at lambda = 1 the model takes G(-1) = Fm and its
       // derivative -G'(-1), so the step is 1 + (Fm - F1)/F'(-1).
       double lp = xn, pd = 1.0, rpd = 1.0, st = 0.0;
@@ -1134,7 +1139,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
         st = pv * rpd;
         lp -= st;
       }
-      if (!(fabs(st) <= 0x1p-26)) {
+      if (!(fabs(st) <= (small ? 0x1p-22 : 0x1p-26))) {
         const double g = aa + lp * (-bb + lp * (cc - dd * lp));
         const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
         const double pv = lp * lp * g - G1;
