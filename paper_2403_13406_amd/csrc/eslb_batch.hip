@@ -42,10 +42,12 @@ struct BatchInst {
   Phys P;
 };
 
+constexpr int kMaxPass = 64;  // passes per composed step the control block has queues for
 struct BatchCtl {
   long long step;     // lockstep step counter
   int active_tiles;   // tiles of instances that still have steps to do
   int active;         // number of such instances
+  unsigned next[kMaxPass];  // per pass: the next tile for the persistent grid (zeroed every step)
 };
 
 // Offsets are kept modulo the grid: omod[i] = (o mod nx, o mod ny) of instance i at
@@ -74,55 +76,88 @@ __device__ __forceinline__ unsigned boffset(int k, int x, int y, int nx, int ny,
   return ((unsigned)ys * (unsigned)nx + (unsigned)xs) * 8u;
 }
 
-__device__ __forceinline__ double& bat(double* base, unsigned byte_off) {
-  return *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off);
+// A state pointer read from the instance table is a generic pointer to the
+// compiler (flat loads and stores, 64-bit per-lane addresses); the states live in
+// global memory, so the accesses go through a global-address-space pointer: the
+// plane's base is uniform (scalar registers) and each access is that base plus a
+// 32-bit per-lane byte offset.
+using gchar = __attribute__((address_space(1))) char;
+using gdouble = __attribute__((address_space(1))) double;
+__device__ __forceinline__ gdouble& bat(const gchar* plane, unsigned byte_off) {
+  return *reinterpret_cast<gdouble*>(const_cast<gchar*>(plane) + byte_off);
 }
 
-// One relaxation pass (pass p of the step) over every active tile.
+// One relaxation pass (pass p of the step) over every active tile.  queue = 0:
+// one block per tile of the whole table (blocks past the active prefix return at
+// once).  queue = 1: a persistent grid whose blocks take tiles from the pass's
+// counter (ctl->next[p]) until the active tiles are exhausted, so that blocks
+// that drew cheap tiles (fast root searches) go on to take more.
 template <class S, int D, int BX, int BY>
 __global__ __launch_bounds__(BX* BY, 2) void k_batch_stage(const BatchInst* __restrict__ inst,
-                                                          const TileRef* __restrict__ tiles, const BatchCtl* ctl,
+                                                          const TileRef* __restrict__ tiles, BatchCtl* ctl,
                                                           const int2* __restrict__ omod, const int2* __restrict__ cmod,
-                                                          int npass, int p, int mode, int omega_one, DevStats* st) {
+                                                          int npass, int p, int mode, int omega_one, int queue,
+                                                          DevStats* st) {
   constexpr int Q = S::Q, M = S::M;
+  __shared__ int next_tile;
   const int ntiles = ctl->active_tiles;
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  int tile = (int)blockIdx.x;
+  if (queue) {
+    if (threadIdx.x == 0) next_tile = (int)atomicAdd(&ctl->next[p], 1u);
+    __syncthreads();
+    tile = next_tile;
+  }
+  for (;;) {
+    if (tile >= ntiles) break;
+    // the next tile is taken now, so that the atomic's round trip overlaps this tile's work
+    int pre = 0;
+    if (queue && threadIdx.x == 0) pre = (int)atomicAdd(&ctl->next[p], 1u);
     const TileRef tr = tiles[tile];
     const int i = tr.inst;
     const BatchInst& b = inst[i];
     const int x = tr.tx * BX + (int)(threadIdx.x % BX);
     const int y = tr.ty * BY + (int)(threadIdx.x / BX);
-    if (x >= b.nx || y >= b.ny) continue;
-    const int2 om = omod[i], cm = cmod[i * npass + p];
-    int mx = om.x + cm.x, my = om.y + cm.y;
-    if (mx >= b.nx) mx -= b.nx;
-    if (my >= b.ny) my -= b.ny;
-    const unsigned pb = (unsigned)b.nx * (unsigned)b.ny * 8u;  // plane bytes
-    unsigned off[Q];
-    double f[Q][M];
+    if (x < b.nx && y < b.ny) {
+      const int2 om = omod[i], cm = cmod[i * npass + p];
+      int mx = om.x + cm.x, my = om.y + cm.y;
+      if (mx >= b.nx) mx -= b.nx;
+      if (my >= b.ny) my -= b.ny;
+      const size_t pb = (size_t)b.nx * (size_t)b.ny * 8u;  // plane bytes
+      const gchar* base = (const gchar*)b.f;
+      unsigned off[Q];
+      double f[Q][M];
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      off[k] = boffset<D>(k, x, y, b.nx, b.ny, mx, my);
+      for (int k = 0; k < Q; ++k) {
+        off[k] = boffset<D>(k, x, y, b.nx, b.ny, mx, my);
 #pragma unroll
-      for (int m = 0; m < M; ++m) f[k][m] = bat(b.f, off[k] + (unsigned)(k * M + m) * pb);
-    }
-    unsigned flags = 0;
-    Phys P = b.P;
-    if (omega_one) P.omega = 1.0;
-    relax_node<S>(f, mode, P, flags);
-    bool fin = true;
-#pragma unroll
-    for (int k = 0; k < Q; ++k)
-#pragma unroll
-      for (int m = 0; m < M; ++m) {
-        fin &= isfinite(f[k][m]);
-        bat(b.f, off[k] + (unsigned)(k * M + m) * pb) = f[k][m];
+        for (int m = 0; m < M; ++m) f[k][m] = bat(base + (k * M + m) * pb, off[k]);
       }
-    if (!fin) flags |= FLAG_NAN;
-    if (flags) {
-      atomicOr(&st->flags, flags);
-      if (flags & FLAG_FALLBACK) atomicAdd(&st->n_fallback, 1ull);
+      unsigned flags = 0;
+      Phys P = b.P;
+      if (omega_one) P.omega = 1.0;
+      relax_node<S>(f, mode, P, flags);
+      // offsets as 32-bit values of this block (see k_stage)
+#pragma unroll
+      for (int k = 0; k < Q; ++k) asm volatile("" : "+v"(off[k]));
+      bool fin = true;
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          fin &= isfinite(f[k][m]);
+          bat(base + (k * M + m) * pb, off[k]) = f[k][m];
+        }
+      if (!fin) flags |= FLAG_NAN;
+      if (flags) {
+        atomicOr(&st->flags, flags);
+        if (flags & FLAG_FALLBACK) atomicAdd(&st->n_fallback, 1ull);
+      }
     }
+    if (!queue) break;
+    __syncthreads();  // every thread has read next_tile before it is overwritten
+    if (threadIdx.x == 0) next_tile = pre;
+    __syncthreads();
+    tile = next_tile;
   }
 }
 
@@ -130,7 +165,7 @@ __global__ __launch_bounds__(BX* BY, 2) void k_batch_stage(const BatchInst* __re
 // grid); thread 0 advances the counter and shrinks the active prefix.
 __global__ void k_batch_advance(BatchCtl* ctl, const long long* __restrict__ steps_sorted,
                                 const int* __restrict__ tiles_prefix, const BatchInst* __restrict__ inst,
-                                int2* __restrict__ omod, int n) {
+                                int2* __restrict__ omod, int n, int npass) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const BatchInst& b = inst[i];
@@ -148,6 +183,7 @@ __global__ void k_batch_advance(BatchCtl* ctl, const long long* __restrict__ ste
     ctl->step = s;
     ctl->active = a;
     ctl->active_tiles = tiles_prefix[a];
+    for (int q = 0; q < npass; ++q) ctl->next[q] = 0u;
   }
 }
 
@@ -159,13 +195,14 @@ __global__ void k_batch_reset(BatchCtl* ctl, int active, int tiles, const BatchI
     ctl->step = 0;
     ctl->active = active;
     ctl->active_tiles = tiles;
+    for (int q = 0; q < kMaxPass; ++q) ctl->next[q] = 0u;
   }
 }
 
 // blocks_per_cu = 0: one block per tile of the whole table (the blocks past the
 // active prefix return at once), so the hardware dispatcher balances the tiles
 // whose root searches take longer; otherwise a persistent grid of that many
-// blocks per CU strides over the tiles.
+// blocks per CU that takes tiles from a per-pass queue.
 struct Config {
   int bx, by, blocks_per_cu;
 };
@@ -203,11 +240,12 @@ int bhip(eslb_batch* b, hipError_t e, const char* what) {
 
 template <class S, int D>
 void launch_cfg(const Config& c, int grid, hipStream_t st, const BatchInst* inst, const TileRef* tiles,
-                const BatchCtl* ctl, const int2* omod, const int2* cmod, int npass, int p, int mode, int om1,
+                BatchCtl* ctl, const int2* omod, const int2* cmod, int npass, int p, int mode, int om1,
                 DevStats* ds) {
+  const int queue = c.blocks_per_cu > 0 ? 1 : 0;
 #define L(BX, BY)                                                                                                  \
   hipLaunchKernelGGL((k_batch_stage<S, D, BX, BY>), dim3(grid), dim3(BX * BY), 0, st, inst, tiles, ctl, omod, cmod, \
-                     npass, p, mode, om1, ds)
+                     npass, p, mode, om1, queue, ds)
   if (c.bx == 64 && c.by == 4) L(64, 4);
   else if (c.bx == 128 && c.by == 2) L(128, 2);
   else if (c.bx == 256 && c.by == 1) L(256, 1);
@@ -217,7 +255,7 @@ void launch_cfg(const Config& c, int grid, hipStream_t st, const BatchInst* inst
 }
 
 void launch_kind(int kind, const Config& c, int grid, hipStream_t st, const BatchInst* inst, const TileRef* tiles,
-                 const BatchCtl* ctl, const int2* omod, const int2* cmod, int npass, int p, int mode, int om1,
+                 BatchCtl* ctl, const int2* omod, const int2* cmod, int npass, int p, int mode, int om1,
                  DevStats* ds) {
 #define CALL(S, D) launch_cfg<S, D>(c, grid, st, inst, tiles, ctl, omod, cmod, npass, p, mode, om1, ds)
   ESLB_DISPATCH_KIND(kind, CALL)
@@ -257,6 +295,7 @@ int build_tables(eslb_batch* b, const Config& cfg, double* const* f, const std::
   const int n = (int)order.size();
   const eslb_ctx* c = b->proto;
   const int npass = (int)c->passes.size();
+  if (npass > kMaxPass) return berr(b, ESLB_ERR_INVALID_ARG, "batch: schedule has more passes per step than supported");
   const long long net = net_shift(c);
   std::vector<BatchInst> hi(n);
   std::vector<int> first(n + 1, 0), prefix(n + 1, 0);
@@ -331,7 +370,7 @@ int capture_steps(eslb_batch* b, const Config& cfg, const RunTables& T, int k, h
                   ps.op == PASS_PROJECT ? 1 : 0, c->st);
     }
     hipLaunchKernelGGL(k_batch_advance, dim3((T.nact + 255) / 256), dim3(256), 0, b->cap, T.ctl, T.steps_sorted,
-                       T.tiles_prefix, T.inst, T.omod, T.nact);
+                       T.tiles_prefix, T.inst, T.omod, T.nact, npass);
   }
   rc = bhip(b, hipStreamEndCapture(b->cap, &g), "end capture");
   if (rc != ESLB_OK) return rc;
