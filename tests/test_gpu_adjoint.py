@@ -7,7 +7,10 @@ Through several steps the two forward recomputations differ by rounding
 input through grad omega, which is bounded but has a derivative of size 1/|d|
 (omega(f) is Lipschitz, not smooth, at equilibrium).  Nodes where d is tiny
 (extrema of smooth data) therefore amplify that rounding by ~1/|d|: the bar
-there is 1e-10 in the normwise L2 sense and 1e-9 in max-norm.
+there is 1e-10 in the normwise L2 sense and 1e-9 in max-norm.  Measured on an
+MI355X (the tests print them): Euler and 2D shallow water 1.6e-13 .. 1.1e-12 (L2)
+and 2.0e-13 .. 1.3e-12 (max); the 1D cases, whose smooth data hold more nodes with
+tiny d, 1.4e-11 .. 2.8e-11 (L2) and 6.5e-11 .. 1.5e-10 (max).
 """
 import numpy as np
 import pytest
@@ -56,9 +59,10 @@ def test_adjoint_through_steps(name, nsteps, ck):
     want = adjoint_run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u), nsteps, fbarT)
     got = to_host(fb)
     err = componentwise_error(got, want)
+    l2s = [np.linalg.norm(got[:, m] - want[:, m]) / np.linalg.norm(want[:, m]) for m in range(want.shape[1])]
+    print("%s, %d steps: max-norm %.2e, L2 %.2e" % (name, nsteps, max(err), max(l2s)))
     assert max(err) <= 1e-9, err
-    for m in range(want.shape[1]):
-        l2 = np.linalg.norm(got[:, m] - want[:, m]) / np.linalg.norm(want[:, m])
+    for m, l2 in enumerate(l2s):
         assert l2 <= MULTI_STEP_L2, (m, l2)
 
 
@@ -130,9 +134,10 @@ def test_taped_and_recomputing_workspaces(name, scheme, nsteps, ck):
     want = adjoint_run(Relaxer(lat, sys, w.V, "entropic"), equilibrium(lat, sys, w.V, u), nsteps, fbarT,
                        scheme=scheme)
     err = componentwise_error(outs[1], want)
+    l2s = [np.linalg.norm(outs[1][:, m] - want[:, m]) / np.linalg.norm(want[:, m]) for m in range(want.shape[1])]
+    print("%s, scheme %d, %d steps: max-norm %.2e, L2 %.2e" % (name, scheme, nsteps, max(err), max(l2s)))
     assert max(err) <= 1e-9, err
-    for m in range(want.shape[1]):
-        l2 = np.linalg.norm(outs[1][:, m] - want[:, m]) / np.linalg.norm(want[:, m])
+    for m, l2 in enumerate(l2s):
         assert l2 <= MULTI_STEP_L2, (m, l2)
 
 
