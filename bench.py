@@ -315,7 +315,7 @@ def adjoint_compare(torch, n, nsteps, ckpt, fd_dirs=0, minimal=True):
     head = rec[modes[0][0]]
     rec["forward_plus_adjoint_s"] = head["forward_plus_adjoint_s"]
     rec["ratio_to_forward"] = head["ratio_to_forward"]
-    rec["taped"] = modes[0][1]
+    rec["headline_workspace"] = modes[0][0]
     if fd_dirs:
         rng = np.random.default_rng(w.extra["fd_seed"])
         gnorm = float(torch.linalg.vector_norm(g))
