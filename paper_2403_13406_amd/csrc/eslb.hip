@@ -883,16 +883,20 @@ void launch_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   }
 }
 
-// The stage and adjoint-stage kernels on D2Q4 grids: 64 x 2 blocks (two waves,
-// each one 64-node row segment).  Their waves run for very different times (root
-// searches), and a smaller block frees its CU slots sooner: 1% faster than 64 x 4
-// on the 4096^2 Euler and SW2D passes, 0.7% on the 1024^2 Euler forward + adjoint;
-// D1Q2 keeps 256 threads (smaller blocks measured slower).
+// The stage and adjoint-stage kernels on D2Q4 grids: 128-thread blocks (two
+// waves).  Their waves run for very different times (root searches), and a
+// smaller block frees its CU slots sooner: 64 x 2 was 1% faster than 64 x 4 on the
+// 4096^2 Euler and SW2D passes, 0.7% on the 1024^2 Euler forward + adjoint; 128 x 1
+// (one row per block) takes another 1.6% off the Euler pass and 1.3% off the
+// forward + adjoint.  D1Q2 keeps 256 threads (smaller blocks measured slower).
 void stage_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
   launch_shape(c, grid, block);
   if (c->d == 2) {
-    // kLdsStride = 128 threads: 64 x 2, or 32 x 4 on grids narrower than 64
-    const int bx = c->pb.nx >= 64 ? 64 : 32, by = kLdsStride / bx;
+    // kLdsStride = 128 threads: 128 x 1 on grids at least 128 wide (a wave's row
+    // segment then spans 1 KiB of each plane, and the partially covered 128-B
+    // lines at the ends of the x-shifted segments cost half as much: 4096^2 Euler
+    // FETCH_SIZE -5.6%, pass -1.6% against 64 x 2), else 64 x 2 or 32 x 4
+    const int bx = c->pb.nx >= 128 ? 128 : (c->pb.nx >= 64 ? 64 : 32), by = kLdsStride / bx;
     block = dim3(bx, by, 1);
     grid = dim3((unsigned)(((long long)c->pb.nx + bx - 1) / bx), (unsigned)(((long long)c->pb.ny + by - 1) / by), 1);
   }
