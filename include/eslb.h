@@ -289,7 +289,9 @@ void eslb_batch_destroy(eslb_batch* batch);
 /* Advance instance i by nsteps[i] >= 0 composed steps, in place.  f_devs[i]: its
  * state (q*M planes of nx_i*ny_i, storage layout with the instance's offsets; may
  * be NULL when nsteps[i] == 0).  Synchronises with the batch's own stream before
- * returning (the caller's stream is made to wait for it as well). */
+ * returning (the caller's stream is made to wait for it as well).  Errors:
+ * ESLB_ERR_INVALID_ARG (NULL argument, negative step count, a schedule of more
+ * than 64 passes per step), ESLB_ERR_HIP. */
 int eslb_batch_run(eslb_batch* batch, double* const* f_devs, const int64_t* nsteps);
 /* Offsets of instance i (q entries, all equal: transport moves every velocity by
  * the same number of cells). */
@@ -298,8 +300,10 @@ int eslb_batch_set_offsets(eslb_batch* batch, int32_t i, const int64_t* offsets)
 /* Synchronise and return the sticky status of the whole batch. */
 int eslb_batch_sync_status(eslb_batch* batch);
 /* Launch configuration: tile block_x x block_y (64x4, 64x2, 128x2, 256x1, 32x8),
- * persistent blocks per compute unit (0: one block per tile, dispatched by the
- * hardware), composed steps per captured graph. */
+ * blocks per compute unit of a persistent grid whose blocks take tiles from a
+ * per-pass queue (0: one block per tile, dispatched by the hardware), composed
+ * steps per captured graph.  Errors: ESLB_ERR_INVALID_ARG (NULL batch, a tile
+ * shape not listed, blocks_per_cu < 0, steps_per_graph < 1). */
 int eslb_batch_set_config(eslb_batch* batch, int32_t block_x, int32_t block_y, int32_t blocks_per_cu,
                           int32_t steps_per_graph);
 int eslb_batch_get_config(const eslb_batch* batch, int32_t* cfg4);
