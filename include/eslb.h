@@ -299,7 +299,7 @@ int eslb_batch_get_offsets(const eslb_batch* batch, int32_t i, int64_t* offsets)
 int eslb_batch_set_offsets(eslb_batch* batch, int32_t i, const int64_t* offsets);
 /* Synchronise and return the sticky status of the whole batch. */
 int eslb_batch_sync_status(eslb_batch* batch);
-/* Launch configuration: tile block_x x block_y (64x4, 64x2, 128x2, 256x1, 32x8),
+/* Launch configuration: tile block_x x block_y (64x4, 64x2, 128x2, 128x1, 256x1, 32x8),
  * blocks per compute unit of a persistent grid whose blocks take tiles from a
  * per-pass queue (0: one block per tile, dispatched by the hardware), composed
  * steps per captured graph.  Errors: ESLB_ERR_INVALID_ARG (NULL batch, a tile

@@ -207,8 +207,8 @@ struct Config {
   int bx, by, blocks_per_cu;
 };
 
-const Config kConfigs[] = {{64, 4, 8}, {64, 4, 4}, {64, 4, 16}, {128, 2, 8}, {256, 1, 8},
-                           {32, 8, 8}, {64, 2, 8}, {64, 4, 0}, {64, 2, 0}};
+const Config kConfigs[] = {{64, 4, 8}, {64, 4, 4}, {64, 4, 16}, {128, 2, 8}, {256, 1, 8}, {32, 8, 8},
+                           {64, 2, 8}, {64, 4, 0}, {64, 2, 0}, {128, 1, 0}, {128, 1, 8}};
 
 }  // namespace
 
@@ -251,6 +251,7 @@ void launch_cfg(const Config& c, int grid, hipStream_t st, const BatchInst* inst
   else if (c.bx == 256 && c.by == 1) L(256, 1);
   else if (c.bx == 32 && c.by == 8) L(32, 8);
   else if (c.bx == 64 && c.by == 2) L(64, 2);
+  else if (c.bx == 128 && c.by == 1) L(128, 1);
 #undef L
 }
 
