@@ -436,27 +436,39 @@ template <int D> struct ShallowWater {
     const double P1 = gV * a * (b + cq) + W2 * W * (2.0 * s * gn - x1 * W);
     const double P2 = gV * a * a + W2 * (gn - 2.0 * s * x1 * W);
     const double P3 = -x1 * W2;
-    // start from the third-order series reversion of the root about dn = 0,
-    // d0 (1 - q + 2 q^2 - r) with d0 = -P0/P1, q = P2 d0 / P1, r = P3 d0^2 / P1
-    // (error O(dn^4)), while its corrections are small changes of the first Newton
-    // iterate from 0 (|q|, |r| <= 1/4); otherwise from that iterate itself.  Then
-    // Newton, stopped once the error its recurrence leaves after a step,
-    // |P''/(2P')| st^2, is below 2^-53 |dn|: near the cell state one step.
+    // The root about dn = 0 by series reversion: with d0 = -P0/P1, q = P2 d0 / P1,
+    // r = P3 d0^2 / P1, dn = d0 z and z = 1 - q z^2 - r z^3, i.e.
+    //   z = 1 - q + 2q^2 - 5q^3 + 14q^4 - r + 5qr - 21q^2 r + 3r^2 + O(5)
+    // (q of first order, r of second).  Near the cell state (|q| <= 2^-12,
+    // |r| <= 2^-24) the fourth-order sum is the root to below 2^-52 relative and
+    // no Newton step is taken.  Otherwise start from the third-order sum
+    // d0 (1 - q + 2 q^2 - r) (error O(dn^4)) while its corrections are small changes
+    // of the first Newton iterate from 0 (|q|, |r| <= 1/4), else from that iterate
+    // itself, and run Newton, stopped once the error its recurrence leaves after a
+    // step, |P''/(2P')| st^2, is below 2^-53 |dn|.
     const double rP1 = rcp(P1);
     const double d0 = -P0 * rP1;
     const double q = P2 * d0 * rP1, r = P3 * d0 * d0 * rP1;
-    double dn = (fabs(q) <= 0.25 && fabs(r) <= 0.25) ? d0 * (1.0 - q + (2.0 * q * q - r)) : d0;
+    double dn;
     bool conv = false;
+    if ((fabs(q) <= 0x1p-12) & (fabs(r) <= 0x1p-24)) {
+      const double zq = fma(-q, fma(-q, fma(-q, fma(-14.0, q, 5.0), 2.0), 1.0), 1.0);
+      const double zr = r * fma(-3.0, r, fma(-q, fma(-21.0, q, 5.0), 1.0));
+      dn = d0 * (zq - zr);
+      conv = true;
+    } else {
+      dn = (fabs(q) <= 0.25 && fabs(r) <= 0.25) ? d0 * (1.0 - q + (2.0 * q * q - r)) : d0;
 #pragma unroll 1
-    for (int it = 0; it < 12; ++it) {
-      const double Pv = P0 + dn * (P1 + dn * (P2 + dn * P3));
-      const double dP = P1 + dn * (2.0 * P2 + 3.0 * P3 * dn);
-      const double rdP = rcp(dP);
-      const double st = Pv * rdP;
-      dn -= st;
-      if (!(fabs(P2 + 3.0 * P3 * dn) * fabs(rdP) * st * st > 0x1p-53 * fabs(dn))) {
-        conv = true;
-        break;
+      for (int it = 0; it < 12; ++it) {
+        const double Pv = P0 + dn * (P1 + dn * (P2 + dn * P3));
+        const double dP = P1 + dn * (2.0 * P2 + 3.0 * P3 * dn);
+        const double rdP = rcp(dP);
+        const double st = Pv * rdP;
+        dn -= st;
+        if (!(fabs(P2 + 3.0 * P3 * dn) * fabs(rdP) * st * st > 0x1p-53 * fabs(dn))) {
+          conv = true;
+          break;
+        }
       }
     }
     // Far from the cell state (no convergence, |dn| > W/20, or a root outside the
