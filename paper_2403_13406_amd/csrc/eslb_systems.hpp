@@ -1133,16 +1133,19 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
       // within |lambda - 1| of 1, and its second derivative over twice its first is
       // about 1/2, so the error after j steps is about 2 (|lambda - 1| / 2)^(2^j):
       // three steps leave it below 2^-55 wherever |lambda - 1| < 2^-6 (the
-      // predictor's skip region and far beyond); the third is taken only where the
-      // second was not already below 2^-26, or, where the prediction is taken as
-      // the root (small), below 2^-22: the error after it is then below 2^-45, and
-      // the update moves f^eq - lambda d by that times |d| <= 2^-8 |f| about (the
-      // skip region): below rounding.  The reciprocals need no more than 2^-48.
+      // predictor's skip region and far beyond); the second and third are taken
+      // only where the previous step was not already below 2^-26, or, where the
+      // prediction is taken as the root (small), below 2^-22: the error after it is
+      // then below 2^-45, and the update moves f^eq - lambda d by that times
+      // |d| <= 2^-8 |f| about (the skip region): below rounding.  The reciprocals
+      // need no more than 2^-48.
       // The first step is xn: at lambda = 1 the model takes G(-1) = Fm and its
-      // derivative -G'(-1), so the step is 1 + (Fm - F1)/F'(-1).
+      // derivative -G'(-1), so the step is 1 + (Fm - F1)/F'(-1).  Each further step
+      // is taken only while the previous one was above the limit (after a step st
+      // the error is about st^2 / 2).
       double lp = xn, pd = 1.0, rpd = 1.0, st = 0.0;
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      const double st_lim = small ? 0x1p-22 : 0x1p-26;
+      const auto newton = [&]() {
         const double g = aa + lp * (-bb + lp * (cc - dd * lp));
         const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
         const double pv = lp * lp * g - G1;
@@ -1150,14 +1153,11 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
         rpd = rcp1(pd);
         st = pv * rpd;
         lp -= st;
-      }
-      if (!(fabs(st) <= (small ? 0x1p-22 : 0x1p-26))) {
-        const double g = aa + lp * (-bb + lp * (cc - dd * lp));
-        const double gp = -bb + lp * (2.0 * cc - 3.0 * dd * lp);
-        const double pv = lp * lp * g - G1;
-        pd = 2.0 * lp * g + lp * lp * gp;
-        rpd = rcp1(pd);
-        lp -= pv * rpd;
+      };
+      newton();
+      if (!(fabs(st) <= st_lim)) {
+        newton();
+        if (!(fabs(st) <= st_lim)) newton();
       }
       if (isfinite(lp) && lp > lo && lp < hi && pd > 0.0) {
         // close to equilibrium the prediction is within the stopping tolerance
