@@ -135,7 +135,8 @@ __global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes p
                                                                DevStats* st, Planes rec, double* lamr) {
   constexpr int Q = S::Q, M = S::M;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int by = g.rev ? (int)(gridDim.y - 1u - blockIdx.y) : (int)blockIdx.y;
+  const int y = by * blockDim.y + threadIdx.y;
   const bool act = (x < g.nx) && (y < g.ny);
   unsigned flags = 0;
   double om = 2.0;
@@ -859,6 +860,7 @@ Grid make_grid(const eslb_ctx* c, double* f) {
   g.f = f;
   g.nx = c->pb.nx;
   g.ny = c->pb.ny;
+  g.rev = 0;
   g.plane = (long long)c->pb.nx * c->pb.ny;
   for (int k = 0; k < 4; ++k) g.sh[k] = 0;
   for (int k = 0; k < c->q; ++k) {
@@ -907,7 +909,13 @@ void stage_shape(const eslb_ctx* c, dim3& grid, dim3& block) {
 // rec (optional): q*M planes that receive the pass input, and lamr (optional
 // with rec; needed for mode 1) one plane for lambda; see k_stage.
 int launch_stage(eslb_ctx* c, double* f, int mode, double* rec, double* lamr) {
-  const Grid g = make_grid(c, f);
+  Grid g = make_grid(c, f);
+  // Every other pass takes the block rows in reverse order, so that it starts on
+  // the rows the previous pass ended with, whose lines the memory-side cache
+  // (256 MB, an eighth of a 4096^2 Euler state) still holds: 4096^2 Euler,
+  // fixed omega 816 -> 762 us per pass, entropic 830 -> 815 us (same box).  Each
+  // node's arithmetic does not depend on the order: the same bits.
+  g.rev = (int)(c->stage_launches++ & 1u);
   dim3 grid, block;
   stage_shape(c, grid, block);
   const int track = (mode == 1) ? c->track : 0;

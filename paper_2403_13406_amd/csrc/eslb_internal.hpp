@@ -29,6 +29,7 @@ struct Grid {
   long long plane;  // nx * ny
   int nx, ny;
   int sh[4];        // logical node x of velocity k is stored at x + sh[k] (mod n) along its axis
+  int rev;          // stage passes: block rows taken in reverse order (see launch_stage)
 };
 
 enum Kind { KIND_ADV1, KIND_ADV2, KIND_BUR1, KIND_BUR2, KIND_SW1, KIND_SW2, KIND_EU2 };
@@ -77,6 +78,7 @@ struct eslb_ctx {
   int diag_blocks = 0;
   double* scratch = nullptr;     // device address of the static diagnostics scratch on this context's device
   int track = 0;
+  unsigned stage_launches = 0;  // parity of the row order of the next stage pass
   bool small_run = false;  // whole run in one workgroup's LDS (small states)
   int fused_L = 0, fused_H = 0;  // fused D1Q2 step: owned cells per block, halo (0: not available)
   int fused_L_small = 0;         // owned cells per block for states of one workgroup (one cell per thread)

@@ -146,13 +146,13 @@ __device__ __forceinline__ void phi_pair_wide(double za, double zb, double& pa, 
   }
 }
 
-// 1/(1 + z) for |z| <= 2^-10.5 from its geometric series to z^4 (truncation
-// below |z|^5 < 2^-52 relative)
+// 1/(1 + z) for |z| <= 2^-10.5 from its geometric series to z^3 (truncation
+// below |z|^4 < 2^-42 relative: it enters F' and the gradient of omega only,
+// which need no more; see the Euler evaluation)
 __device__ __forceinline__ double recip1p_small(double z) {
-  double r = z - 1.0;
-  r = fma(z, r, 1.0);
-  r = fma(z, r, -1.0);
-  return fma(z, r, 1.0);
+  // 1 - z + z^2 - z^3 = (1 + z^2)(1 - z)
+  const double a = fma(z, z, 1.0);
+  return fma(-z, a, a);
 }
 
 // Threshold of the predictor's skip measure (z / m^2, see Euler2 and
@@ -700,8 +700,10 @@ struct Euler2 {
     double ix1, dn;  // 1/x_1, dn
     bool okd = true;
     if (fabs(eps) < 0x1p-11) {
-      double cat = fma(14.0, eps, 5.0);
-      cat = fma(cat, eps, 2.0);
+      // 1 + eps (1 + eps (2 + eps (5 + 14 eps))), the innermost level as
+      // eps (4 + 14 eps) + (eps + 2): inline constants only (no register to
+      // materialise 5 in every evaluation)
+      double cat = fma(eps, fma(eps, 14.0, 4.0), eps + 2.0);
       cat = fma(cat, eps, 1.0);
       cat = fma(cat, eps, 1.0);
       ix1 = qb * r;
@@ -1096,6 +1098,9 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
       okm &= isfinite(Fm);
     }
     if (!ok1) {
+      // d = 0 exactly: omega = 2 with no search (the callers that test d before
+      // the search never get here with it)
+      if (!(src.dmax() > 0.0)) return 1.0;
       fallback = !S::pending(c);
       return 0.0;
     }
@@ -1301,9 +1306,9 @@ __device__ __forceinline__ double relax_node_lds(double (&f)[S::Q][S::M], int mo
   constexpr int Q = S::Q, M = S::M;
   static_assert(S::kTolFromU, "LDS-held d needs the stop tolerance from u");
   double u[M];
-  bool nz;
   {
     double feq[Q][M], d[Q][M];
+    bool nz;  // not needed here: see below
     node_split<S>(f, u, feq, d, nz, P);
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
@@ -1319,15 +1324,21 @@ __device__ __forceinline__ double relax_node_lds(double (&f)[S::Q][S::M], int mo
     if (!adm) flags |= FLAG_INADMISSIBLE;
 #pragma unroll
     for (int i = 0; i < Q / 2; ++i) slot[(Q * M + i) * kLdsStride] = c.vel[i];
+    // As relax_node: omega = 2 at equilibrium (d = 0), omega = 1 where the cell is
+    // inadmissible and d is not 0, else the root.  The d = 0 test is left to the
+    // paths where it decides something (inadmissible cells, and the root search's
+    // out-of-domain exit: entropic_lambda), so admissible cells skip it: with d = 0
+    // the search returns lambda = 1 at its F(1) > 0 test.
+    const LdsSrc<S> src{slot, u, P};
     lam = 1.0;
-    if (nz) {
-      fallback = !adm;
+    if (adm) {
+      lam = entropic_lambda<S>(c, src, u, P, fallback);
+    } else {
+      fallback = src.dmax() > 0.0;
+    }
+    if (fallback) {
       lam = 0.0;
-      if (adm) lam = entropic_lambda<S>(c, LdsSrc<S>{slot, u, P}, u, P, fallback);
-      if (fallback) {
-        lam = 0.0;
-        flags |= FLAG_FALLBACK;
-      }
+      flags |= FLAG_FALLBACK;
     }
   }
   // f^eq rebuilt from u with the velocity and pressure of prepare (the same bits
