@@ -550,9 +550,14 @@ template <int D> struct ShallowWaterFast : ShallowWater<D> {
 
 struct Euler2 {
   static constexpr int D = 2, M = 4, Q = 4;
-  // resident 256-thread blocks per CU asked of the stage kernel: three waves per
-  // SIMD (168 VGPRs), which the LDS-held d makes room for
-  static constexpr int kStageBlocks = 3;
+  // resident 256-thread blocks per CU asked of the stage kernel: four waves per
+  // SIMD (128 VGPRs), which the LDS-held d makes room for.  The hot path (the
+  // predictor shortcut) does not spill; the safeguarded search does (its max|d|
+  // and stop tolerance, a few dozen bytes per lane).  With the alternating row
+  // order, whose passes leave the kernel waiting on memory more than on its
+  // arithmetic, the fourth wave hides more of that wait: 4096^2 pass 816 -> 801 us
+  // against three waves (168 VGPRs, no spills), same box.
+  static constexpr int kStageBlocks = 4;
   static constexpr bool kTolFromU = true;  // see stop_tol
   static constexpr bool kSweepFinite = true;  // eval leaves the finiteness of B to fsum
   static constexpr bool kLdsD = true;      // stage kernel keeps d in LDS (relax_node_lds)
