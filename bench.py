@@ -13,7 +13,9 @@ One JSON line:
                around the timed steps (stage kernels only): algorithmic bytes per
                launch (2 q M 8 B per node) / average launch time vs 8 TB/s;
                traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (calibrated
-               on a plain copy), from profiles/ when the kernel sources still match
+               on a plain copy), from profiles/ when the kernel sources still match;
+               floor (full run, 2D) = the same stage kernel with fixed omega
+               (its loads and stores without the root search), same measure
   alu          (when profiles/ holds a VALU counter record of the same sources) the
                same launches against the FP64 vector peak and the VALU issue peak
   cpu_baseline the CPU oracle, single-threaded, on a bounded sample of the workload
@@ -121,6 +123,27 @@ def timed_steps(s, f, steps, torch):
     return ev0.elapsed_time(ev1)
 
 
+def fixed_omega_floor(torch, w, steps=2):
+    """The same stage kernel with fixed omega, per-pass launches (no fusion): the entropic
+    pass's loads and stores with almost none of its arithmetic, i.e. the floor that this
+    access pattern meets on this memory system."""
+    from paper_2403_13406_amd import Solver
+    u0 = torch.from_numpy(w.initial_state()).cuda()
+    s = Solver(w.lattice, w.system, w.nx, w.ny, V=w.V, relax="fixed", omega=2.0, param=w.param, fused=False)
+    f = s.init_equilibrium(u0)
+    del u0
+    s.step(f, 1)
+    s.sync()
+    ms = timed_steps(s, f, steps, torch)
+    assert s.sync() == 0
+    us = ms * 1e3 / (steps * 18)
+    gbs = 2 * s.q * s.M * 8 * w.cells / (us * 1e-6) / 1e9
+    del f
+    s.close()
+    return {"kernel": "the same stage kernel with fixed omega (no root search), per-pass launches",
+            "us_per_launch": round(us, 2), "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def bench_single(args, torch):
     from paper_2403_13406_amd import Solver
     w = make_workload(args.workload, args.size)
@@ -156,8 +179,7 @@ def bench_single(args, torch):
         roofline["traffic_over_algorithmic"] = round(traffic["bytes_per_launch"] / bytes_per_launch, 4)
     alu = None
     if valu:
-        # secondary views of the same launches: the entropic pass is limited by FP64
-        # arithmetic issue, not by its bytes.  FP64 FLOPs per node (ADD + MUL + 2 FMA +
+        # secondary views of the same launches.  FP64 FLOPs per node (ADD + MUL + 2 FMA +
         # TRANS lane instructions) against the 78.6 TFLOP/s vector peak, and VALU issue
         # slots (every VALU instruction takes a SIMD's 16 lanes four cycles per wave, an
         # FP64 transcendental four times that) against the issue peak at 2.4 GHz and at
@@ -197,6 +219,8 @@ def bench_single(args, torch):
     if alu:
         rec["alu"] = alu
     del f
+    if not args.no_extras and w.lattice == "D2Q4":
+        roofline["floor"] = fixed_omega_floor(torch, w)
     return rec, w
 
 

@@ -128,10 +128,11 @@ constexpr size_t stage_lds_bytes() {
 // order; NaN where the root search fell back), so the adjoint pass needs no
 // copy of its input and no root search.
 template <class S, int D, bool Off32, bool Rec = false>
-// S::kStageBlocks blocks of 256 threads per CU: two waves per SIMD for the heavy
-// systems (fewer registers than the unconstrained build's one wave, no spilling;
-// measured 1.40x faster on the Euler stage), four for 1D shallow water
-__global__ __launch_bounds__(256, S::kStageBlocks) void k_stage(Grid g, Planes pl, Phys P, int mode, int track,
+// S::kStageBlocks (recording form: S::kRecBlocks) resident blocks of 256 threads
+// per CU, i.e. that many waves per SIMD and 512 / that many VGPRs: four for the
+// Euler pass and 1D shallow water, three for the Euler recording pass, two for
+// the other 2D systems (see each system)
+__global__ __launch_bounds__(256, Rec ? S::kRecBlocks : S::kStageBlocks) void k_stage(Grid g, Planes pl, Phys P, int mode, int track,
                                                                DevStats* st, Planes rec, double* lamr) {
   constexpr int Q = S::Q, M = S::M;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;

@@ -176,6 +176,7 @@ template <> struct Lat<2> {
 // (Example "Linear transport equation", Sec. 1.2.1 and 1.2.2).
 template <int D> struct Advection {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  static constexpr int kRecBlocks = kStageBlocks;  // the same for its recording form
   static constexpr bool kTolFromU = false;  // see stop_tol
   static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
@@ -216,6 +217,7 @@ template <int D> struct Advection {
 // c1 = w + beta u / (2V); B = dU^2 (w/2 + beta (3u + 2 dU) / (12V)).
 template <int D> struct Burgers {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  static constexpr int kRecBlocks = kStageBlocks;  // the same for its recording form
   static constexpr bool kTolFromU = false;  // see stop_tol
   static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
@@ -348,6 +350,7 @@ template <int D> struct ShallowWaterFast;
 
 template <int D> struct ShallowWater {
   static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  static constexpr int kRecBlocks = kStageBlocks;  // the same for its recording form
   static constexpr bool kTolFromU = false;  // see stop_tol
   static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
@@ -558,6 +561,9 @@ struct Euler2 {
   // arithmetic, the fourth wave hides more of that wait: 4096^2 pass 816 -> 801 us
   // against three waves (168 VGPRs, no spills), same box.
   static constexpr int kStageBlocks = 4;
+  // the recording form (the adjoint's reruns, which also store the pass input)
+  // stays at three waves (168 VGPRs, no spills): at four, 1024^2 69.3 -> 71.3 us
+  static constexpr int kRecBlocks = 3;
   static constexpr bool kTolFromU = true;  // see stop_tol
   static constexpr bool kSweepFinite = true;  // eval leaves the finiteness of B to fsum
   static constexpr bool kLdsD = true;      // stage kernel keeps d in LDS (relax_node_lds)
