@@ -130,8 +130,8 @@ constexpr size_t stage_lds_bytes() {
 template <class S, int D, bool Off32, bool Rec = false>
 // S::kStageBlocks (recording form: S::kRecBlocks) resident blocks of 256 threads
 // per CU, i.e. that many waves per SIMD and 512 / that many VGPRs: four for the
-// Euler pass and 1D shallow water, three for the Euler recording pass, two for
-// the other 2D systems (see each system)
+// Euler pass and 1D shallow water, three for the Euler recording pass and 2D
+// shallow water, two for the 2D scalar systems (see each system)
 __global__ __launch_bounds__(256, Rec ? S::kRecBlocks : S::kStageBlocks) void k_stage(Grid g, Planes pl, Phys P, int mode, int track,
                                                                DevStats* st, Planes rec, double* lamr) {
   constexpr int Q = S::Q, M = S::M;

@@ -93,7 +93,7 @@ __device__ __forceinline__ gdouble& bat(const gchar* plane, unsigned byte_off) {
 // counter (ctl->next[p]) until the active tiles are exhausted, so that blocks
 // that drew cheap tiles (fast root searches) go on to take more.
 template <class S, int D, int BX, int BY>
-__global__ __launch_bounds__(BX* BY, 2) void k_batch_stage(const BatchInst* __restrict__ inst,
+__global__ __launch_bounds__(BX* BY, S::kBatchBlocks) void k_batch_stage(const BatchInst* __restrict__ inst,
                                                           const TileRef* __restrict__ tiles, BatchCtl* ctl,
                                                           const int2* __restrict__ omod, const int2* __restrict__ cmod,
                                                           int npass, int p, int mode, int omega_one, int queue,

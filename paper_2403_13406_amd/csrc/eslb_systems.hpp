@@ -177,6 +177,7 @@ template <> struct Lat<2> {
 template <int D> struct Advection {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int kRecBlocks = kStageBlocks;  // the same for its recording form
+  static constexpr int kBatchBlocks = 2;  // the same for the batch stage kernel
   static constexpr bool kTolFromU = false;  // see stop_tol
   static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
@@ -218,6 +219,7 @@ template <int D> struct Advection {
 template <int D> struct Burgers {
   static constexpr int kStageBlocks = 2;  // resident 256-thread blocks per CU asked of the stage kernel
   static constexpr int kRecBlocks = kStageBlocks;  // the same for its recording form
+  static constexpr int kBatchBlocks = 2;  // the same for the batch stage kernel
   static constexpr bool kTolFromU = false;  // see stop_tol
   static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
@@ -349,8 +351,13 @@ __device__ inline double sw_branch_root(double P0, double P1, double P2, double 
 template <int D> struct ShallowWaterFast;
 
 template <int D> struct ShallowWater {
-  static constexpr int kStageBlocks = (D == 1) ? 4 : 2;  // resident 256-thread blocks per CU asked of the stage kernel
+  // resident 256-thread blocks per CU asked of the stage kernel (waves per SIMD):
+  // 2D at three (168 VGPRs; the spills cost less than the third wave gains:
+  // 512-instance ensemble at a tenth of its steps, batch 7.57 -> 6.84 s and the
+  // per-instance loop 11.7 -> 11.2 s against two waves; four lose, 8.25 s)
+  static constexpr int kStageBlocks = (D == 1) ? 4 : 3;
   static constexpr int kRecBlocks = kStageBlocks;  // the same for its recording form
+  static constexpr int kBatchBlocks = 3;  // the same for the batch stage kernel
   static constexpr bool kTolFromU = false;  // see stop_tol
   static constexpr bool kSweepFinite = false;  // see fsum
   static constexpr bool kLdsD = false;
@@ -564,6 +571,7 @@ struct Euler2 {
   // the recording form (the adjoint's reruns, which also store the pass input)
   // stays at three waves (168 VGPRs, no spills): at four, 1024^2 69.3 -> 71.3 us
   static constexpr int kRecBlocks = 3;
+  static constexpr int kBatchBlocks = 2;  // batch stage kernel (d in registers: 2 waves)
   static constexpr bool kTolFromU = true;  // see stop_tol
   static constexpr bool kSweepFinite = true;  // eval leaves the finiteness of B to fsum
   static constexpr bool kLdsD = true;      // stage kernel keeps d in LDS (relax_node_lds)
