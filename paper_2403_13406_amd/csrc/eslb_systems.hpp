@@ -614,7 +614,7 @@ struct Euler2 {
   // limit of the skip measure: 2^-8 m^2, m = 1 - c^2/W_min^2 (negative: never skip)
   __device__ static double skip_limit(const Node& c, const Phys& P) {
     const double Wmin = P.W0 - fmax(fabs(c.vel[0]), fabs(c.vel[1]));
-    const double m = 1.0 - c.cs2 * rcp(Wmin * Wmin);
+    const double m = 1.0 - c.cs2 * rcp1(Wmin * Wmin);  // a threshold: 2^-48 is plenty
     return (Wmin > 0.0 && m > 0.0) ? kSkipZ * m * m : -1.0;
   }
   __device__ static bool subchar(const Node& c, const Phys& P) {
@@ -713,7 +713,9 @@ struct Euler2 {
     // vanishes: eps is then not finite) the closed form with a square root.  (On
     // smooth 4096^2 Euler data |eps| stays below 2^-11.)
     const double aq = P.q0 * qcx;
-    const double r = rcp(x1 * qb);
+    // once refined (relative error about 2^-48, the size of the series' truncation;
+    // the closed form below has its own reciprocal)
+    const double r = rcp1(x1 * qb);
     const double iqb = x1 * r;
     const double eps = aq * (iqb * iqb);
     double ix1, dn;  // 1/x_1, dn
@@ -761,14 +763,16 @@ struct Euler2 {
       okx = okd & (x1 > 0.0) & (zb > -1.0) & (al > -1.0);
     }
     const double du2 = fma(dn, dn, dt * dt);
-    B = fma(x1, fma(du2, c.hbet, fma(pa, igm1, pb)), (s * c.sbet) * dp * dn);
+    const double pab = fma(pa, igm1, pb);  // phi(za)/(gamma-1) + phi(zb)
+    B = fma(x1, fma(du2, c.hbet, pab), (s * c.sbet) * dp * dn);
     if (DV) {
       // entropy-variable difference v(U_k) - v(u): with ds = log1p(za) + (gamma-1) log1p(zb),
       //   v(U_k) - v(u) = (-ds/(gamma-1) - (beta'|u'|^2 - beta|u|^2)/2, beta' u' - beta u, -(beta' - beta)),
       // so its dot product with d_k is -ds d_1/(gamma-1) + beta' Q(u') - beta Q(u), Q as in vel_consts,
       // with Q(u') = Q(u) + dQ, dQ = dn (d_n - u_n d_1) + dt (d_t - u_t d_1) - |du|^2 d_1/2
       // and beta' Q(u') - beta Q(u) = beta (dQ - za Q(u)) / (1 + za)
-      const double ds = (za - pa) + (P.p0 - 1.0) * (zb - pb);
+      // ds = (za - pa) + (gamma-1) (zb - pb) = za + (gamma-1) (zb - pab)
+      const double ds = fma(P.p0 - 1.0, zb - pab, za);
       const double dQ = fma(K.hd0, du2, fma(dn, K.gnd, dt * K.dtn));
       dvd = fma(-ds, K.d0g, (c.bet * ira) * fma(-za, K.Q0, dQ));
       if (DVV) {
@@ -829,7 +833,7 @@ struct Euler2 {
   // measure at t = -1 only), from one read of its LDS slots: the per-velocity
   // constants are formed once and t is a constant in each evaluation.  The second
   // evaluation starts once the first is summed (interleaved, they need more
-  // registers than three waves per SIMD allow).
+  // registers than the stage kernel's waves per SIMD allow).
   template <int k>
   __device__ static void pair_fresh(const Node& c, const double* vel, double f1, const double* d, const Phys& P,
                                     double zlim, double& F1, double& dF1, bool& ok1, double& Fm, double& dFm,
@@ -1146,7 +1150,7 @@ __device__ inline double entropic_lambda(const typename S::Node& c, const Src& s
     } else {
       lo = 1.0;
     }
-    double xn = okm ? 1.0 + H * rcp(dFm) : NAN;  // Newton from lambda = 1 (H' = -F'(-1))
+    double xn = okm ? 1.0 + H * rcp1(dFm) : NAN;  // Newton from lambda = 1 (H' = -F'(-1)); a start only
     if (okm) {
       const double G1 = F1, Gm = Fm, G1p = dF1 - 2.0 * F1, Gmp = dFm + 2.0 * Fm;
       const double cc = 0.25 * (G1p - Gmp);
