@@ -201,7 +201,7 @@ template <int D> struct Advection {
   __device__ static void fluxT(const Node&, int j, const double* z, double* out, const Phys& P) { out[0] = a(j, P) * z[0]; }
   template <int k, bool DV>
   __device__ static bool bregman(const Node&, const double*, const double* d, double t, double& B, double* dv,
-                                 const Phys& P, double zlim, bool& small) {
+                                 const Phys& P, double /*zlim: no skip measure*/, bool& small) {
     small = false;
     const double wk = P.w + Lat<D>::sign(k) * a(Lat<D>::axis(k), P) * P.inv2V;
     const double dU = t * d[0] / wk;
@@ -244,7 +244,7 @@ template <int D> struct Burgers {
   }
   template <int k, bool DV>
   __device__ static bool bregman(const Node& c, const double*, const double* d, double t, double& B, double* dv,
-                                 const Phys& P, double zlim, bool& small) {
+                                 const Phys& P, double /*zlim: no skip measure*/, bool& small) {
     small = false;
     const double beta = Lat<D>::sign(k) * b(Lat<D>::axis(k), P);
     const double e = t * d[0];
@@ -690,13 +690,11 @@ struct Euler2 {
   // B_k(t); DV: the F' term dvd = (v(U_k) - v(u)) . d_k; DVV: also the difference
   // v(U_k) - v(u) itself in dv (the adjoint's gradient of omega needs it)
   template <int k, bool DV, bool DVV = DV>
-  __device__ static bool eval(const Node& c, double un, double ut, double f1, double d0, double dn_, double dt_,
-                              double d3, const VelC& K, double t, double& B, double& dvd, double* dv, const Phys& P,
-                              double zlim, bool& small) {
+  __device__ static bool eval(const Node& c, double un, double ut, double f1, double d0, const VelC& K, double t,
+                              double& B, double& dvd, double* dv, const Phys& P, double zlim, bool& small) {
     constexpr int n = Lat<2>::axis(k), tt = 1 - n;
     constexpr double s = Lat<2>::sign(k);
     const double igm1 = P.p2, V2 = P.V2;
-    const double rho = c.rho;
     const double e1 = t * d0;
     const double x1 = f1 + e1;
     const double tdtn = t * K.dtn;
@@ -803,7 +801,7 @@ struct Euler2 {
     const double un = c.vel[n], ut = c.vel[tt];
     const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
     double dvd;
-    return eval<k, DV, DV>(c, un, ut, feq[0], d0, dn_, dt_, d3, K, t, B, dvd, dv, P, zlim, small);
+    return eval<k, DV, DV>(c, un, ut, feq[0], d0, K, t, B, dvd, dv, P, zlim, small);
   }
   // bregman returning the F' term (v(U_k) - v(u)) . d_k itself (fsum's form for this system)
   template <int k, bool DV>
@@ -815,7 +813,7 @@ struct Euler2 {
     const double un = c.vel[n], ut = c.vel[tt];
     const VelC K = vel_consts<k>(c, un, ut, d0, dn_, dt_, d3, P);
     double dv[4];
-    return eval<k, DV, false>(c, un, ut, feq[0], d0, dn_, dt_, d3, K, t, B, dvd, dv, P, zlim, small);
+    return eval<k, DV, false>(c, un, ut, feq[0], d0, K, t, B, dvd, dv, P, zlim, small);
   }
   // bregman for values just read from thread-private LDS slots (LdsSrc), the cell
   // velocity (vel) included: no copies, and nothing derived from them is kept
@@ -826,7 +824,7 @@ struct Euler2 {
     constexpr int n = Lat<2>::axis(k), tt = 1 - n;
     const VelC K = vel_consts<k>(c, vel[n], vel[tt], d[0], d[1 + n], d[1 + tt], d[3], P);
     double dv[4];
-    return eval<k, DV, false>(c, vel[n], vel[tt], feq[0], d[0], d[1 + n], d[1 + tt], d[3], K, t, B, dvd, dv, P, zlim,
+    return eval<k, DV, false>(c, vel[n], vel[tt], feq[0], d[0], K, t, B, dvd, dv, P, zlim,
                               small);
   }
   // The predictor's two samples for velocity k, t = +1 and t = -1 (the skip
@@ -844,11 +842,11 @@ struct Euler2 {
     double B, dvd, dv[4];
     bool sk;
     // the same sums as fsum's, so that the register path (relax_node) gives the same bits
-    ok1 &= eval<k, true, false>(c, un, ut, f1, d0, dn_, dt_, d3, K, 1.0, B, dvd, dv, P, -1.0, sk);
+    ok1 &= eval<k, true, false>(c, un, ut, f1, d0, K, 1.0, B, dvd, dv, P, -1.0, sk);
     F1 = (k == 0) ? B : F1 + B;  // the callers start the sums at 0
     dF1 = (k == 0) ? dvd : dF1 + dvd;
     asm volatile("" : "+v"(f1), "+v"(d0) : "v"(F1), "v"(dF1));
-    okm &= eval<k, true, false>(c, un, ut, f1, d0, dn_, dt_, d3, K, -1.0, B, dvd, dv, P, zlim, sk);
+    okm &= eval<k, true, false>(c, un, ut, f1, d0, K, -1.0, B, dvd, dv, P, zlim, sk);
     small &= sk;
     Fm = (k == 0) ? B : Fm + B;
     dFm = (k == 0) ? dvd : dFm + dvd;
