@@ -1,6 +1,6 @@
 """Benchmark of the fourth-order entropy-stable LB time loop on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler2d|sw1d|burgers1d|batch|adjoint|aux]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload euler2d|sw1d|burgers1d|batch|adjoint|aux|floor]
 
 A "step" is one composed fourth-order step Phi(dt) (eq. splittingToUse): 18
 passes "shift, entropic relax" over the whole grid.  The default workload is the
@@ -34,7 +34,8 @@ One JSON line:
                seconds, with the paper's own (other GPU) times beside them
 --workload batch / adjoint run only those two comparisons (the adjoint one with all 32
 directions);
---workload aux times init, moments, gather and diagnostics at the 4096^2 Euler size.
+--workload aux times init, moments, gather and diagnostics at the 4096^2 Euler size;
+--workload floor times only the fixed-omega stage pass of the roofline's floor.
 """
 import argparse
 import json
@@ -506,6 +507,15 @@ def main():
         print(json.dumps({"metric": "time and GB/s of the kernels around the stage passes", "n_gpus": 1,
                           "dtype": "f64", "data": "synthetic", "config": {"workload": r["workload"]},
                           "aux": r["kernels"]}), flush=True)
+        return
+    if args.workload == "floor":
+        # the fixed-omega form of the 4096^2 Euler stage pass alone (the `floor` of the
+        # default run's roofline), for a kernel trace of that measurement
+        w = make_workload("euler2d", args.size)
+        r = fixed_omega_floor(torch, w, steps=max(1, min(args.steps, 20)))
+        print(json.dumps({"metric": "stage pass time, fixed omega", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "%s_%dx%d" % (w.name, w.nx, w.ny), "relax": "fixed"},
+                          "floor": r}), flush=True)
         return
     if args.workload == "adjoint":
         r = adjoint_compare(torch, 1024, 2000, 50, 32 if args.fd_dirs is None else args.fd_dirs)
